@@ -1,0 +1,112 @@
+"""Oracle geometry: solid set, ghost (solid boundary) nodes, solid normals,
+probe points x_F = x_G + n_s and their interpolation weights.  Checked by
+brute force in numpy and by the properties the construction must have."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_30878_amd import workloads as W
+
+
+def _velocities(lattice):
+    return oracle.lattice_tables(lattice)["c"]
+
+
+def _brute_sets(wl):
+    nx, ny, nz = wl.shape
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    solid = np.zeros((nz, ny, nx), bool)
+    for s in wl.solids:
+        if s.kind == 0:
+            d2 = (x - s.center[0]) ** 2 + (y - s.center[1]) ** 2
+            if wl.lattice == W.D3Q19:
+                d2 = d2 + (z - s.center[2]) ** 2
+            solid |= d2 <= s.radius ** 2
+        else:
+            v = (x - s.center[0]) * s.normal[0] + (y - s.center[1]) * s.normal[1]
+            if wl.lattice == W.D3Q19:
+                v = v + (z - s.center[2]) * s.normal[2]
+            solid |= v <= 0
+    c = _velocities(wl.lattice)
+    fluid_nb = np.zeros_like(solid)
+    solid_nb_links = np.zeros(solid.shape, np.int64)
+    for ci in c[1:]:
+        sh = np.roll(solid, shift=(-ci[2], -ci[1], -ci[0]), axis=(0, 1, 2))  # solid[x + c]
+        fluid_nb |= ~sh
+        solid_nb_links += sh
+    ghost = solid & fluid_nb
+    links = int(solid_nb_links[~solid].sum())
+    fb = int(((solid_nb_links > 0) & ~solid).sum())
+    return solid.reshape(-1), ghost.reshape(-1), links, fb
+
+
+@pytest.mark.parametrize("wl", [W.cylinder_d2q9_128(), W.sphere_d3q19(64),
+                                W.plate_d2q9(40, 24, 60.0, 10.0)],
+                         ids=["cyl128", "sphere64", "plate"])
+def test_solid_and_ghost_sets_brute_force(wl):
+    sim = oracle.OracleSim(wl, W.initial_phi(wl))
+    solid, ghost, links, fb = _brute_sets(wl)
+    info = sim.info()
+    assert info["n_solid"] == solid.sum()
+    assert info["n_ghost"] == ghost.sum()
+    assert info["n_links"] == links
+    assert info["n_fluid_boundary"] == fb
+    ids, nrm, corners, weights = sim.ghosts()
+    assert np.array_equal(ids, np.flatnonzero(ghost))
+    assert np.array_equal(sim.get(oracle.F_SOLID) > 0.5, solid)
+
+
+def test_config_counts():
+    """Counts for the two main boxes (closed-ball solids)."""
+    s1 = oracle.OracleSim(W.cylinder_d2q9_128(), W.initial_phi(W.cylinder_d2q9_128()))
+    assert s1.info()["n_solid"] == 1793 and s1.info()["n_ghost"] == 188
+    assert s1.info()["n_links"] == 464 and s1.info()["n_fluid_boundary"] == 200
+    wl = W.sphere_d3q19(64)
+    s2 = oracle.OracleSim(wl, W.initial_phi(wl))
+    assert s2.info()["n_solid"] == 7153 and s2.info()["n_ghost"] == 2088
+    assert s2.info()["n_links"] == 10242
+
+
+@pytest.mark.parametrize("wl", [W.cylinder_d2q9_128(), W.sphere_d3q19(64)], ids=["cyl128", "sphere64"])
+def test_probe_points_and_weights(wl):
+    """n_s is the unit outward normal of the ball; the weights are the
+    bi/trilinear weights of x_F = x_G + n_s: non-negative, sum 1, and they
+    reproduce x_F (linear fields are interpolated exactly)."""
+    sim = oracle.OracleSim(wl, W.initial_phi(wl))
+    ids, nrm, corners, weights = sim.ghosts()
+    nx, ny, nz = wl.shape
+    D = 3 if wl.lattice == W.D3Q19 else 2
+    xs = np.stack([ids % nx, (ids // nx) % ny, ids // (nx * ny)], axis=1).astype(float)
+    c = np.asarray(wl.solids[0].center)
+    r = xs - c
+    r[:, D:] = 0
+    want_n = r / np.linalg.norm(r, axis=1, keepdims=True)
+    assert np.allclose(nrm, want_n, atol=1e-15)
+    nc = 2 ** D
+    assert np.all(weights[:, :nc] >= 0)
+    assert np.allclose(weights[:, :nc].sum(axis=1), 1.0, atol=1e-15)
+    xf = xs + nrm
+    cx = np.stack([corners % nx, (corners // nx) % ny, corners // (nx * ny)], axis=2).astype(float)
+    # unwrap corners to the neighbourhood of x_F
+    L = np.array([nx, ny, nz], float)
+    d = cx - xf[:, None, :]
+    cx = cx - L * np.round(d / L)
+    interp = (weights[:, :nc, None] * cx[:, :nc, :]).sum(axis=1)
+    assert np.allclose(interp[:, :D], xf[:, :D], atol=1e-13)
+    # x_F lies within one node spacing of every corner used
+    assert np.all(np.abs(cx[:, :nc, :D] - xf[:, None, :D]) < 1.0 + 1e-12)
+
+
+def test_flat_wall_probe_is_a_node():
+    """On a grid-aligned flat wall x_F is the node one spacing into the fluid
+    (weight 1): the flat-wall limit of the curved-boundary rule."""
+    wl = W.plate_d2q9(40, 24, 60.0, 10.0)
+    sim = oracle.OracleSim(wl, W.initial_phi(wl))
+    ids, nrm, corners, weights = sim.ghosts()
+    nx = wl.shape[0]
+    for g in range(len(ids)):
+        k = int(np.argmax(weights[g, :4]))
+        assert weights[g, k] == 1.0
+        y = ids[g] // nx
+        want_y = 1 if y == 0 else wl.shape[1] - 2
+        assert corners[g, k] == ids[g] % nx + nx * want_y
