@@ -1,0 +1,186 @@
+/*
+ * lbm.h -- C ABI of the MI355X colour-gradient lattice Boltzmann library
+ * with the curved-boundary ghost-node wetting condition.
+ *
+ * One time step (lbm_step) follows the paper's model:
+ *   colour field phi = sum_i B_i                       (Appendix A, Eq. A13)
+ *   ghost-node colour update at every solid boundary   (Section 2, Eq. 9;
+ *     node, phi_G = phi_F / (phi_F + (1-phi_F) e^eps)   Eq. 10 as a switch)
+ *     with phi_F interpolated at x_F = x_G + n_s
+ *   forces F_s (Eq. 4), F_p (Eq. A10), F_visc (Eq. A11), F_b (Eq. 2)
+ *   MRT collision of the colour-blind populations N    (Eq. A1-A3, A4, A8)
+ *   recolouring of the liquid populations B            (Eq. A12)
+ *   streaming of N and B with halfway bounce-back      (Eq. A16-A17)
+ * on a D2Q9 or D3Q19 lattice, every axis periodic; walls are solids.
+ *
+ * Conventions
+ *   - Every function returns an int: LBM_OK (0) or a negative LBM_E* code;
+ *     lbm_last_error() then holds a message.  No function aborts.
+ *   - A context is not thread-safe; use one thread per context.
+ *   - Node (x, y, z) has flat index x + nx*(y + ny*z).  Host arrays passed in
+ *     or out are FP64 in that order; per-direction arrays are [Q][nodes] in
+ *     the direction order returned by lbm_lattice().
+ *   - The library allocates no device memory.  The caller (PyTorch) owns one
+ *     device buffer and one HIP stream and hands them over with lbm_bind();
+ *     the buffer must stay alive and unused by others until lbm_destroy().
+ *   - Device work is enqueued on the bound stream.  lbm_step() does not
+ *     synchronise; lbm_observe(), lbm_read_field() and lbm_set_field() do.
+ *     A kernel error of lbm_step() is reported by the next synchronising call.
+ *   - Call order: lbm_create -> lbm_set_geometry -> lbm_device_bytes ->
+ *     lbm_bind -> lbm_set_wetting -> lbm_set_field(LBM_FIELD_PHI) ->
+ *     lbm_step / lbm_observe / lbm_read_field ... -> lbm_destroy.
+ *     Out-of-order calls return LBM_ESTATE.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_ABI_VERSION 1u
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* bad argument or parameter */
+    LBM_ESTATE = -2,     /* call out of order */
+    LBM_ENOMEM = -3,     /* bound buffer too small, or a host allocation failed */
+    LBM_EHIP = -4,       /* HIP runtime or kernel error */
+    LBM_EUNSTABLE = -5   /* lbm_observe found non-finite values */
+};
+
+enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
+
+/* Population storage.  Arithmetic is FP64 for LBM_FP64 and FP32 otherwise. */
+enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_OFS = 2, LBM_BF16_OFS = 3 };
+
+/* Ghost-node rule: Eq. 9 (this paper) or Eq. 10 (Fakhari et al.). */
+enum { LBM_GHOST_EQ9 = 0, LBM_GHOST_FAKHARI = 1 };
+
+/* Fields for lbm_set_field / lbm_read_field (all FP64 on the host). */
+enum {
+    LBM_FIELD_PHI = 0,        /* [nodes] colour field phi.  set: initial phi at
+                                 fluid nodes (N_i = chi_i, B_i = phi chi_i, u = p = 0);
+                                 read: the phi (fluid and ghost nodes) the next
+                                 step will use */
+    LBM_FIELD_N = 1,          /* [Q][nodes] colour-blind populations (post-stream) */
+    LBM_FIELD_B = 2,          /* [Q][nodes] liquid populations (post-stream) */
+    LBM_FIELD_U = 3,          /* [3][nodes] velocity u of Eq. A14 (read only) */
+    LBM_FIELD_P = 4,          /* [nodes] auxiliary pressure p of Eq. A15 (read only) */
+    LBM_FIELD_SOLID_PHI = 5,  /* [nodes] phi carried at solid nodes between steps */
+    LBM_FIELD_FLAGS = 6       /* [nodes] node class: 1 solid, 2 fluid next to a
+                                 solid, 4 ghost (read only) */
+};
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Model parameters, lattice units (dx = dt = 1).  Defaults of the paper's
+ * Section 3: rho_l = 1000, rho_g = 1, mu_l = 10, mu_g = 0.1, sigma = 0.01,
+ * W = 4, mobility = 0.02. */
+typedef struct {
+    uint32_t abi_version;   /* LBM_ABI_VERSION */
+    uint32_t lattice;       /* LBM_D2Q9 or LBM_D3Q19 */
+    uint32_t precision;     /* LBM_FP64 ... */
+    uint32_t ghost_rule;    /* LBM_GHOST_EQ9 or LBM_GHOST_FAKHARI */
+    int32_t n[3];           /* box nodes; n[2] must be 1 for D2Q9 */
+    int32_t pad;
+    double rho_l, rho_g;    /* liquid (phi = 1) and gas (phi = 0) densities, > 0 */
+    double mu_l, mu_g;      /* dynamic viscosities, > 0 */
+    double sigma;           /* surface tension, >= 0 */
+    double W;               /* interface width, >= 4 (Section 2, text after Eq. 9) */
+    double mobility;        /* M_phi > 0; sets the colour weights (Eq. A7) */
+    double body_accel[3];   /* g of the body force rho g (Eq. 2) */
+} lbm_params;
+
+/* Solid primitive.  kind 0: ball (disk in 2D) |x - center| <= radius, closed.
+ * kind 1: half-space (x - center) . normal <= 0; normal points out of the
+ * solid.  A node's solid normal n_s is that of the first primitive holding it
+ * (radial for a ball, `normal` normalised for a half-space). */
+typedef struct {
+    uint32_t kind;
+    uint32_t pad;
+    double center[3];
+    double radius;
+    double normal[3];
+} lbm_solid;
+
+/* Diagnostics, FP64, summed over fluid nodes in a fixed order. */
+typedef struct {
+    int64_t step;            /* steps taken since the last LBM_FIELD_PHI set */
+    int64_t n_fluid, n_solid, n_ghost;
+    int64_t nonfinite;       /* non-finite N_i, B_i or phi values */
+    double mass_blue;        /* sum phi */
+    double mass_red;         /* sum (1 - phi) */
+    double momentum[3];      /* sum rho u */
+    double max_speed;        /* max |u| (spurious-current measure) */
+    double kinetic_energy;   /* sum rho |u|^2 / 2 */
+} lbm_obs;
+
+/* Validate params and create a context (host memory only).
+ * Errors: LBM_EINVAL for W < 4, non-positive densities/viscosities/mobility,
+ * tau <= 1/2, alpha outside [0, 1), bad lattice/precision/rule/sizes. */
+int lbm_create(const lbm_params* params, lbm_ctx** out);
+
+/* Rasterise `count` solids (host), classify nodes (solid, ghost = solid with
+ * a fluid lattice neighbour, Section 1), and build the ghost list: analytic
+ * normal n_s, probe point x_F = x_G + n_s and its 2^D interpolation corners
+ * and weights (Section 2, text before Eq. 8).  `solids` is read only during
+ * the call.  May be called once, before lbm_bind. */
+int lbm_set_geometry(lbm_ctx* ctx, const lbm_solid* solids, int32_t count);
+
+/* Bytes of device memory lbm_bind needs (known after lbm_set_geometry). */
+int lbm_device_bytes(const lbm_ctx* ctx, size_t* bytes);
+
+/* Hand over a device buffer of at least lbm_device_bytes() bytes (256-byte
+ * aligned) and the HIP stream (hipStream_t, may be NULL for the null stream)
+ * all device work goes to.  Uploads the geometry.  LBM_ENOMEM if too small. */
+int lbm_bind(lbm_ctx* ctx, void* device_ptr, size_t bytes, void* hip_stream);
+
+/* Contact angle theta in degrees through the liquid, 0..180 (Eq. 7);
+ * eps = -(4/W) cos(theta) and exp(eps) are formed on the host in FP64
+ * (Eq. 9).  Before the first step it also sets every solid node to
+ * (1 + cos theta)/2 (Section 3); later calls change eps only. */
+int lbm_set_wetting(lbm_ctx* ctx, double theta_deg);
+
+/* Write a field from the host (`count` doubles, see the field list).
+ * LBM_FIELD_PHI starts a run (step counter 0); LBM_FIELD_N / _B /
+ * _SOLID_PHI overwrite raw state (restore).  Synchronises the stream. */
+int lbm_set_field(lbm_ctx* ctx, int field, const double* host_src, size_t count);
+
+/* Enqueue nsteps >= 0 time steps on the bound stream; returns at once. */
+int lbm_step(lbm_ctx* ctx, int64_t nsteps);
+
+/* lbm_step with timing: brackets each of the three launches of every step
+ * (0: colour field, 1: ghost update, 2: fused collide-stream) with HIP
+ * events on the bound stream, waits for the last one, and writes the summed
+ * milliseconds of each phase to ms_out[0..2] and the elapsed time from the
+ * first to the last event to ms_out[3].  nsteps >= 1.  Synchronises. */
+int lbm_step_profiled(lbm_ctx* ctx, int64_t nsteps, double* ms_out);
+
+/* Reduce the diagnostics on the device and copy them out (synchronises).
+ * Returns LBM_EUNSTABLE (and fills *out) if any value is non-finite. */
+int lbm_observe(lbm_ctx* ctx, lbm_obs* out);
+
+/* Copy a field to the host as FP64 (`count` doubles; synchronises).  Solid
+ * nodes read u = p = 0 and N = B = 0. */
+int lbm_read_field(lbm_ctx* ctx, int field, double* host_dst, size_t count);
+
+/* Lattice velocities in the library's direction order: c_out[Q][3] (room for
+ * 19 x 3 int32), *q_out = Q.  No context needed. */
+int lbm_lattice(uint32_t lattice, int32_t* c_out, int32_t* q_out);
+
+/* Release the context's host memory.  The device buffer stays the caller's. */
+int lbm_destroy(lbm_ctx* ctx);
+
+/* Last error message of ctx ("" if none); for ctx == NULL, the last error of
+ * a failed lbm_create on this thread. */
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

@@ -439,9 +439,14 @@ static void colour_field(orc_sim* s) {
 }
 
 /* ---------------------------------------------------------------- geometry */
-static int in_solid(const orc_solid* sd, double x, double y, double z, int D) {
+/* Displacement from a ball centre to a node under the periodic minimum
+ * image (every axis of the box is periodic). */
+static double min_image(double d, long n) { return d - (double)n * floor(d / (double)n + 0.5); }
+
+static int in_solid(const orc_solid* sd, double x, double y, double z, int D, const long* box) {
     if (sd->kind == 0) {
-        double dx = x - sd->c[0], dy = y - sd->c[1], dz = D == 3 ? z - sd->c[2] : 0.0;
+        double dx = min_image(x - sd->c[0], box[0]), dy = min_image(y - sd->c[1], box[1]);
+        double dz = D == 3 ? min_image(z - sd->c[2], box[2]) : 0.0;
         return dx * dx + dy * dy + dz * dz <= sd->r * sd->r;   /* READING R-solid: closed */
     }
     double v = (x - sd->c[0]) * sd->nrm[0] + (y - sd->c[1]) * sd->nrm[1] +
@@ -491,15 +496,18 @@ void* orc_create(const orc_params* P, const orc_solid* solids, int nsolids,
     if (!s->solid || !s->nrm || !s->N || !s->B || !s->Nn || !s->Bn || !s->phi_state || !s->phi || !s->snap)
         FAIL("out of memory");
     /* Solid set and the normal of the first primitive that holds the node. */
+    const long box[3] = {P->nx, P->ny, s->P.nz};
     for (long id = 0; id < n; id++) {
         long x = id % P->nx, y = (id / P->nx) % P->ny, z = id / ((long)P->nx * P->ny);
         for (int k = 0; k < nsolids; k++) {
             const orc_solid* sd = &solids[k];
-            if (!in_solid(sd, (double)x, (double)y, (double)z, D)) continue;
+            if (!in_solid(sd, (double)x, (double)y, (double)z, D, box)) continue;
             s->solid[id] = 1;
             double v[3];
             if (sd->kind == 0) {
-                v[0] = x - sd->c[0]; v[1] = y - sd->c[1]; v[2] = D == 3 ? z - sd->c[2] : 0.0;
+                v[0] = min_image(x - sd->c[0], box[0]);
+                v[1] = min_image(y - sd->c[1], box[1]);
+                v[2] = D == 3 ? min_image(z - sd->c[2], box[2]) : 0.0;
             } else {
                 v[0] = sd->nrm[0]; v[1] = sd->nrm[1]; v[2] = D == 3 ? sd->nrm[2] : 0.0;
             }

@@ -1,0 +1,81 @@
+// launch.h -- interface between the host library (api.cpp) and the HIP
+// kernels (kernels.hip).  Plain structs, no HIP types beyond the stream.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lbm {
+
+// Model constants of one run, FP64 on the host; the launchers round them to
+// the arithmetic type of the run.
+struct StepParams {
+    double rho_l, rho_g;
+    double inv_nu_l, inv_nu_g;  // 1/nu of each phase
+    double sigma, W;
+    double g[3];                // body acceleration
+    double chi[19];             // colour weights (Eq. A7)
+    double chi0;                // chi_0 = alpha
+    double eps;                 // -(4/W) cos(theta)
+    double exp_eps;             // exp(eps), formed on the host
+    double phi_solid;           // (1 + cos theta) / 2
+    int32_t ghost_rule;         // 0 = Eq. 9, 1 = Eq. 10
+    int32_t nx, ny, nz;
+    int64_t n;                  // nodes
+    int64_t S;                  // stride between direction planes (elements)
+};
+
+// Device memory of one run, carved from the caller's buffer.
+struct DevState {
+    void* N[2];         // [Q][S] colour-blind populations, ping-pong
+    void* B[2];         // [Q][S] liquid populations, ping-pong
+    void* phi[2];       // [S] colour field; phi[state] holds the solid values
+    uint8_t* flags;     // [S] node classes
+    int32_t* g_node;    // [n_ghost]
+    int32_t* g_corner;  // [NC][n_ghost] interpolation corners of x_F
+    void* g_w;          // [NC][n_ghost] interpolation weights
+    uint8_t* g_mask;    // [n_ghost] bit k: corner k is a solid node
+    int32_t n_ghost;
+    double* aux;        // [4][S] FP64 scratch: u (3 planes) and p, or a field plane
+    double* partial;    // [REDUCE_BLOCKS][8] reduction partials
+    double* result;     // [8] reduced diagnostics
+    int64_t* nonfinite; // [REDUCE_BLOCKS + 1]
+};
+
+constexpr int REDUCE_BLOCKS = 1024;
+
+enum Precision : uint32_t { P_FP64 = 0, P_FP32 = 1, P_FP16_OFS = 2, P_BF16_OFS = 3 };
+
+// All launchers enqueue on `stream` and return hipGetLastError().
+// `cur` is the population buffer holding the state, `ps` the phi buffer
+// holding the solid values of the state.
+hipError_t launch_step(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
+                       hipStream_t stream);
+// One phase of a step: 0 = colour field, 1 = ghost update, 2 = fused
+// collide-stream (the three launches of launch_step, in that order).
+hipError_t launch_phase(int lattice, uint32_t prec, int phase, const DevState& d, const StepParams& p, int cur,
+                        int ps, hipStream_t stream);
+// Colour field and ghost update into phi[1 - ps] (the phi the next step uses).
+hipError_t launch_colour(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
+                         hipStream_t stream);
+// u and p of every fluid node into aux (after launch_colour).
+hipError_t launch_macro(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
+                        hipStream_t stream);
+// Diagnostics into d.result / d.nonfinite (after launch_macro).
+hipError_t launch_reduce(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
+                         hipStream_t stream);
+// Start of a run from the FP64 phi in aux[0]: N = chi, B = phi chi at fluid
+// nodes, phi of solid nodes (both buffers) = phi_solid.
+hipError_t launch_init(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
+                       hipStream_t stream);
+// Solid nodes of both phi buffers = phi_solid.
+hipError_t launch_solid_phi(uint32_t prec, const DevState& d, const StepParams& p, hipStream_t stream);
+// Convert one plane between storage and FP64 aux[0].  which: 0 = N, 1 = B,
+// 2 = phi buffer `dir`; for N/B, `dir` is the direction, buffer `cur`.
+hipError_t launch_plane_out(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int which,
+                            int dir, int cur, hipStream_t stream);
+hipError_t launch_plane_in(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int which,
+                           int dir, int cur, hipStream_t stream);
+
+}  // namespace lbm

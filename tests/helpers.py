@@ -1,0 +1,67 @@
+"""Shared test helpers: run the HIP library and the oracle on the same seeded
+workload and compare arrays normwise."""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle
+from paper_2605_30878_amd import workloads as W
+
+
+def direction_map(lattice: int) -> np.ndarray:
+    """perm[i] = oracle direction index of library direction i."""
+    from paper_2605_30878_amd import lbm
+
+    c_lib = lbm.lattice(lattice)
+    c_orc = oracle.lattice_tables(lattice)["c"]
+    perm = np.zeros(len(c_lib), dtype=np.int64)
+    for i, c in enumerate(c_lib):
+        m = np.flatnonzero((c_orc == c).all(axis=1))
+        assert m.size == 1
+        perm[i] = m[0]
+    return perm
+
+
+def rel_linf(a: np.ndarray, b: np.ndarray) -> float:
+    """max |a - b| / max |b| (normwise relative L-infinity)."""
+    den = float(np.max(np.abs(b)))
+    if den == 0.0:
+        return float(np.max(np.abs(a)))
+    return float(np.max(np.abs(a - b))) / den
+
+
+def fields_lib(sim, fluid_only_mask=None):
+    from paper_2605_30878_amd import lbm
+
+    return {"N": sim.read(lbm.FIELD_N), "B": sim.read(lbm.FIELD_B), "phi": sim.read(lbm.FIELD_PHI),
+            "u": sim.read(lbm.FIELD_U), "p": sim.read(lbm.FIELD_P), "solid_phi": sim.read(lbm.FIELD_SOLID_PHI)}
+
+
+def fields_orc(osim, perm):
+    solid = osim.get(oracle.F_SOLID) > 0.5
+    N = osim.get(oracle.F_N)[perm]
+    B = osim.get(oracle.F_B)[perm]
+    N[:, solid] = 0.0
+    B[:, solid] = 0.0
+    return {"N": N, "B": B, "phi": osim.get(oracle.F_PHI), "u": osim.get(oracle.F_U),
+            "p": osim.get(oracle.F_P), "solid_phi": osim.get(oracle.F_PHI_STATE), "solid": solid}
+
+
+def compare(lib_f, orc_f, keys=("N", "B", "phi", "u", "p")):
+    solid = orc_f["solid"]
+    out = {}
+    for k in keys:
+        a, b = lib_f[k], orc_f[k]
+        if k in ("phi",):
+            out[k] = rel_linf(a, b)
+        elif k in ("u", "p"):
+            a = a.copy()
+            b = b.copy()
+            a[..., solid] = 0.0
+            b[..., solid] = 0.0
+            out[k] = rel_linf(a, b) if np.max(np.abs(b)) > 1e-300 else float(np.max(np.abs(a)))
+        else:
+            out[k] = rel_linf(a, b)
+    if "solid_phi" in lib_f:
+        out["solid_phi"] = rel_linf(lib_f["solid_phi"][solid], orc_f["solid_phi"][solid]) if solid.any() else 0.0
+    return out

@@ -1,0 +1,129 @@
+"""The C-ABI library on the host: it loads, exports every symbol include/lbm.h
+declares, validates arguments, enforces call order, and its host-side
+geometry (node classes) agrees with the oracle's independent one.  No
+device calls are made."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_30878_amd import lbm
+from paper_2605_30878_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    text = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    return sorted(set(re.findall(r"^\s*(?:int|const char\*)\s+(lbm_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = lbm.load_library()
+    names = _declared_symbols()
+    assert len(names) >= 12
+    for name in names:
+        assert hasattr(lib, name), name
+    assert sorted(names) == sorted(lbm.EXPORTED)
+
+
+def _create(wl, **override):
+    p = lbm.make_params(wl)
+    for k, v in override.items():
+        setattr(p, k, v)
+    h = C.c_void_p()
+    rc = lbm.load_library().lbm_create(C.byref(p), C.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("field,value", [("W", 3.9), ("rho_l", 0.0), ("mu_g", -1.0), ("mobility", 0.0),
+                                         ("mobility", 0.35), ("lattice", 7), ("precision", 9),
+                                         ("ghost_rule", 5), ("abi_version", 99)])
+def test_create_rejects_bad_params(field, value):
+    rc, h = _create(W.cylinder_d2q9_128(), **{field: value})
+    assert rc == lbm.EINVAL
+    assert not h.value
+    assert lbm.load_library().lbm_last_error(None)
+
+
+def test_create_rejects_bad_box():
+    wl = W.cylinder_d2q9_128()
+    p = lbm.make_params(wl)
+    p.n[2] = 2  # D2Q9 needs nz = 1
+    h = C.c_void_p()
+    assert lbm.load_library().lbm_create(C.byref(p), C.byref(h)) == lbm.EINVAL
+    p.n[2] = 1
+    p.n[0] = 0
+    assert lbm.load_library().lbm_create(C.byref(p), C.byref(h)) == lbm.EINVAL
+
+
+def test_call_order_is_enforced():
+    lib = lbm.load_library()
+    rc, h = _create(W.cylinder_d2q9_128())
+    assert rc == lbm.OK
+    nbytes = C.c_size_t()
+    assert lib.lbm_device_bytes(h, C.byref(nbytes)) == lbm.ESTATE
+    assert lib.lbm_step(h, 1) == lbm.ESTATE
+    assert lib.lbm_set_wetting(h, 30.0) == lbm.ESTATE
+    o = lbm.lbm_obs()
+    assert lib.lbm_observe(h, C.byref(o)) == lbm.ESTATE
+    wl = W.cylinder_d2q9_128()
+    assert lib.lbm_set_geometry(h, lbm.make_solids(wl.solids), len(wl.solids)) == lbm.OK
+    assert lib.lbm_set_geometry(h, lbm.make_solids(wl.solids), len(wl.solids)) == lbm.ESTATE
+    assert lib.lbm_device_bytes(h, C.byref(nbytes)) == lbm.OK and nbytes.value > 0
+    assert lib.lbm_bind(h, None, nbytes.value, None) == lbm.EINVAL
+    assert lib.lbm_step(h, 1) == lbm.ESTATE
+    assert lib.lbm_destroy(h) == lbm.OK
+
+
+def test_device_bytes_cover_the_state():
+    """Two population buffers of N and B (Q planes each) plus the rest."""
+    lib = lbm.load_library()
+    wl = W.sphere_d3q19(64, precision=W.FP32)
+    rc, h = _create(wl)
+    assert lib.lbm_set_geometry(h, lbm.make_solids(wl.solids), 1) == lbm.OK
+    nbytes = C.c_size_t()
+    lib.lbm_device_bytes(h, C.byref(nbytes))
+    assert nbytes.value >= 4 * 19 * 64 ** 3 * 4
+    lib.lbm_destroy(h)
+
+
+@pytest.mark.parametrize("wl", [
+    W.cylinder_d2q9_128(),
+    W.sphere_d3q19(64),
+    W.plate_d2q9(40, 24, 60.0, 10.0),
+    # a disk across the periodic corner and two overlapping primitives
+    W.Workload(name="wrap", lattice=W.D2Q9, shape=(37, 29, 1), theta=45.0,
+               solids=[W.Solid(0, (1.5, 2.0, 0.0), 7.3), W.Solid(0, (30.0, 20.0, 0.0), 5.0),
+                       W.Solid(1, (0.0, 24.5, 0.0), normal=(0.3, -1.0, 0.0))]),
+    W.Workload(name="wrap3", lattice=W.D3Q19, shape=(21, 18, 17), theta=45.0,
+               solids=[W.Solid(0, (0.0, 17.0, 8.0), 5.5), W.Solid(0, (10.0, 9.0, 8.0), 4.0)]),
+], ids=["cyl128", "sphere64", "plate", "wrap2d", "wrap3d"])
+def test_node_classes_match_oracle(wl):
+    lib = lbm.load_library()
+    rc, h = _create(wl)
+    assert rc == lbm.OK
+    assert lib.lbm_set_geometry(h, lbm.make_solids(wl.solids), len(wl.solids)) == lbm.OK
+    f = np.zeros(wl.nodes)
+    assert lib.lbm_read_field(h, lbm.FIELD_FLAGS, f.ctypes.data_as(C.POINTER(C.c_double)), wl.nodes) == lbm.OK
+    lib.lbm_destroy(h)
+    flags = f.astype(np.int64)
+    osim = oracle.OracleSim(wl, W.initial_phi(wl))
+    solid = osim.get(oracle.F_SOLID) > 0.5
+    assert np.array_equal((flags & lbm.FLAG_SOLID) > 0, solid)
+    ids, *_ = osim.ghosts()
+    assert np.array_equal(np.flatnonzero(flags & lbm.FLAG_GHOST), ids)
+    assert ((flags & lbm.FLAG_NEAR_SOLID) > 0).sum() == osim.info()["n_fluid_boundary"]
+
+
+def test_lattice_tables():
+    c2 = lbm.lattice(W.D2Q9)
+    c3 = lbm.lattice(W.D3Q19)
+    assert c2.shape == (9, 3) and c3.shape == (19, 3)
+    for c in (c2, c3):
+        assert len({tuple(v) for v in c}) == len(c)
+        assert (c.sum(axis=0) == 0).all()
+    assert np.array_equal(c3[:9], c2)

@@ -1,0 +1,190 @@
+"""GPU parity: the HIP library (through the C ABI) against the FP64 oracle on
+the same seeded inputs.  FP64 runs must match normwise to 1e-12 in every
+population array (N, B) and in phi; FP32 runs are checked against the FP64
+oracle with a tolerance derived from single-precision rounding."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2605_30878_amd import workloads as W
+
+from helpers import compare, direction_map, fields_lib, fields_orc, rel_linf
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _lbm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_30878_amd import lbm
+
+    lbm.load_library()
+    return lbm
+
+
+def _log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _run_pair(wl, checkpoints, tol, keys=("N", "B", "phi", "u", "p")):
+    lbm = _lbm()
+    phi0 = W.initial_phi(wl)
+    _log(f"[parity] {wl.name} shape={wl.shape} prec={wl.precision} theta={wl.theta} steps={checkpoints}")
+    sim = lbm.Simulation(wl, phi0)
+    osim = oracle.OracleSim(wl, phi0)
+    perm = direction_map(wl.lattice)
+    done = 0
+    worst = {}
+    for t in checkpoints:
+        sim.step(t - done)
+        osim.step(t - done)
+        done = t
+        errs = compare(fields_lib(sim), fields_orc(osim, perm), keys)
+        _log(f"  step {t}: " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+        for k, v in errs.items():
+            worst[k] = max(worst.get(k, 0.0), v)
+            assert v <= tol[k] if isinstance(tol, dict) else v <= tol, (t, k, v)
+    ob = sim.observe()
+    oo = osim.observe()
+    assert abs(ob["mass_blue"] - oo["mass_blue"]) <= 1e-9 * max(1.0, abs(oo["mass_blue"]))
+    sim.close()
+    return worst
+
+
+def test_cylinder_d2q9_fp64_parity():
+    """The D2Q9 drop on a cylinder (128^2, theta 90, 2000 steps)."""
+    _run_pair(W.cylinder_d2q9_128(), [1, 10, 100, 2000], TOL64)
+
+
+@pytest.mark.parametrize("theta", [30.0, 150.0])
+def test_cylinder_d2q9_fp64_parity_angles(theta):
+    _run_pair(W.cylinder_d2q9_128(theta=theta), [1, 50, 500], TOL64)
+
+
+def test_sphere_d3q19_fp64_parity_ragged():
+    """D3Q19 with density ratio 1000 and viscosity ratio 100 (exercises the
+    pressure and viscous correction forces) on a box whose x extent is not a
+    multiple of the 64-wide thread rows."""
+    wl = W.Workload(name="d3q19_ragged", lattice=W.D3Q19, shape=(45, 38, 33), rho_l=1000.0, rho_g=1.0,
+                    mu_l=10.0, mu_g=0.1, sigma=0.01, W=4.0, theta=60.0,
+                    solids=[W.Solid(0, (22.0, 19.0, 12.0), 8.5)],
+                    liquid=[W.LiquidRegion("ball", (22.0, 19.0, 21.0), 8.0, width=4.0)])
+    _run_pair(wl, [1, 20, 200], TOL64)
+
+
+def test_plate_d2q9_fp64_parity_walls_density_ratio():
+    """Flat walls (half-space solids), density ratio 10, body force."""
+    wl = W.plate_d2q9(70, 36, 120.0, 12.0, rho_ratio=10.0, mu_ratio=10.0).with_(g=(1e-7, -2e-7, 0.0))
+    _run_pair(wl, [1, 30, 300], TOL64)
+
+
+@pytest.mark.parametrize("theta", [60.0, 90.0])
+def test_fakhari_rule_fp64_parity(theta):
+    """Eq. 10 as the ghost rule (90 deg hits its removable singularity)."""
+    wl = W.cylinder_d2q9_128(theta=theta).with_(ghost_rule=1)
+    _run_pair(wl, [1, 100, 400], TOL64)
+
+
+@pytest.mark.parametrize("theta", [0.0, 180.0])
+def test_extreme_angles_fp64(theta):
+    wl = W.Workload(name="extreme", lattice=W.D2Q9, shape=(50, 44, 1), rho_l=1.0, rho_g=1.0, mu_l=0.1,
+                    mu_g=0.1, W=4.0, theta=theta, solids=[W.Solid(0, (25.0, 15.0, 0.0), 9.0)],
+                    liquid=[W.LiquidRegion("ball", (25.0, 26.0, 0.0), 8.0, width=4.0)])
+    _run_pair(wl, [1, 200], TOL64)
+
+
+def test_no_solid_and_degenerate_boxes_fp64():
+    """No solid at all (empty ghost list), and boxes one node thick."""
+    _run_pair(W.free_drop(W.D2Q9, 40, 9.0, rho_ratio=3.0), [1, 100], TOL64)
+    thin = W.Workload(name="thin", lattice=W.D2Q9, shape=(1, 40, 1), rho_l=1.0, rho_g=1.0, mu_l=0.1,
+                      mu_g=0.1, W=4.0, theta=60.0,
+                      solids=[W.Solid(1, (0.0, 0.5, 0.0), normal=(0.0, 1.0, 0.0))],
+                      liquid=[W.LiquidRegion("below", axis=1, lo=20.0, width=4.0)])
+    _run_pair(thin, [1, 50], TOL64)
+    thin3 = W.Workload(name="thin3", lattice=W.D3Q19, shape=(70, 1, 9), rho_l=1.0, rho_g=1.0, mu_l=0.1,
+                       mu_g=0.1, W=4.0, theta=45.0,
+                       solids=[W.Solid(1, (0.0, 0.0, 1.5), normal=(0.3, 0.0, -1.0))],
+                       liquid=[W.LiquidRegion("slab", axis=0, lo=35.0, hi=60.0, width=4.0)])
+    _run_pair(thin3, [1, 50], TOL64)
+
+
+def test_sphere_d3q19_fp32_short_against_oracle():
+    """FP32 storage and arithmetic against the FP64 oracle over 50 steps at
+    density ratio 1000: single-precision rounding only (normwise 1e-5)."""
+    wl = W.sphere_d3q19(32, theta=60.0, precision=W.FP32)
+    _run_pair(wl, [1, 50], {"N": 1e-5, "B": 1e-5, "phi": 1e-5, "u": 1e-3, "p": 1e-3})
+
+
+def test_observe_and_mass():
+    lbm = _lbm()
+    wl = W.cylinder_d2q9_128()
+    phi0 = W.initial_phi(wl)
+    sim = lbm.Simulation(wl, phi0)
+    osim = oracle.OracleSim(wl, phi0)
+    o0 = sim.observe()
+    sim.step(300)
+    osim.step(300)
+    o1 = sim.observe()
+    oo = osim.observe()
+    assert o1["step"] == 300 and o1["nonfinite"] == 0
+    assert o1["n_ghost"] == 188 and o1["n_solid"] == 1793
+    assert abs(o1["mass_blue"] / o0["mass_blue"] - 1) < 1e-13
+    for k in ("mass_blue", "mass_red", "kinetic_energy", "max_speed"):
+        assert abs(o1[k] - oo[k]) <= 1e-10 * abs(oo[k]), k
+    for a in range(3):
+        assert abs(o1["momentum"][a] - oo["momentum"][a]) <= 1e-10 * max(1e-6, abs(oo["momentum"][a]))
+
+
+def test_restore_roundtrip_is_bitwise():
+    """Raw state read out and written into a fresh context continues
+    bit-identically (checkpoint / resume)."""
+    lbm = _lbm()
+    wl = W.sphere_d3q19(32, theta=120.0, precision=W.FP32)
+    phi0 = W.initial_phi(wl)
+    a = lbm.Simulation(wl, phi0)
+    a.step(25)
+    N, B, S = a.read(lbm.FIELD_N), a.read(lbm.FIELD_B), a.read(lbm.FIELD_SOLID_PHI)
+    b = lbm.Simulation(wl, phi0)
+    b.set_field(lbm.FIELD_N, N)
+    b.set_field(lbm.FIELD_B, B)
+    b.set_field(lbm.FIELD_SOLID_PHI, S)
+    a.step(10)
+    b.step(10)
+    assert np.array_equal(a.read(lbm.FIELD_N), b.read(lbm.FIELD_N))
+    assert np.array_equal(a.read(lbm.FIELD_B), b.read(lbm.FIELD_B))
+
+
+def test_nonfinite_is_reported():
+    lbm = _lbm()
+    wl = W.cylinder_d2q9_128()
+    sim = lbm.Simulation(wl, W.initial_phi(wl))
+    N = sim.read(lbm.FIELD_N)
+    fluid = np.flatnonzero(~((sim.read(lbm.FIELD_FLAGS).astype(int) & 1) > 0))
+    N[3, fluid[100]] = np.nan
+    sim.set_field(lbm.FIELD_N, N)
+    o = sim.observe(allow_unstable=True)
+    assert o["rc"] == lbm.EUNSTABLE and o["nonfinite"] >= 1
+
+
+def test_runtime_argument_errors():
+    lbm = _lbm()
+    wl = W.cylinder_d2q9_128()
+    sim = lbm.Simulation(wl, W.initial_phi(wl))
+    with pytest.raises(lbm.LbmError) as e:
+        sim.set_wetting(181.0)
+    assert e.value.code == lbm.EINVAL
+    with pytest.raises(lbm.LbmError):
+        sim.step(-1)
+    with pytest.raises(lbm.LbmError):
+        sim.set_field(lbm.FIELD_PHI, np.zeros(7))
+    bad = np.full(wl.nodes, np.nan)
+    with pytest.raises(lbm.LbmError):
+        sim.set_field(lbm.FIELD_PHI, bad)
