@@ -77,7 +77,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=256)
     ap.add_argument("--theta", type=float, default=90.0)
-    ap.add_argument("--precision", choices=["f32", "f64"], default="f32")
+    ap.add_argument("--precision", choices=["f32", "f64", "f16ofs", "bf16ofs"], default="f32")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -103,7 +103,7 @@ def main() -> int:
     from paper_2605_30878_amd import lbm
     from paper_2605_30878_amd import workloads as W
 
-    prec = W.FP32 if args.precision == "f32" else W.FP64
+    prec = {"f32": W.FP32, "f64": W.FP64, "f16ofs": W.FP16_OFS, "bf16ofs": W.BF16_OFS}[args.precision]
     wl = W.sphere_d3q19(args.size, theta=args.theta, precision=prec)
     sim = lbm.Simulation(wl, W.initial_phi(wl), device="cuda:0")
     obs0 = sim.observe()
@@ -118,18 +118,23 @@ def main() -> int:
 
     obs1 = sim.observe()
     n_fluid = obs1["n_fluid"]
-    s = 4 if prec == W.FP32 else 8
-    Q = 19
+    s_n = {W.FP64: 8, W.FP32: 4}.get(prec, 2)   # bytes of one stored population
+    s_t = 8 if prec == W.FP64 else 4            # bytes of phi, G, p
+    Q, D = 19, 3
     mlups = wl.nodes * args.steps / (dt * 1e6)
-    # algorithmic bytes of one fused collide-stream launch: N read, N* and B*
-    # written (3 Q s per fluid node), phi read once per fluid node, one flag
-    # byte per box node
-    alg_bytes = n_fluid * (3 * Q * s + s) + wl.nodes
+    # algorithmic bytes of one fused collide-stream launch: per fluid node N
+    # read and N* written (2 Q s_n), phi read once, the compact liquid record
+    # (G, p) written ((D + 1) s_t); one flag byte per box node
+    alg_bytes = n_fluid * (2 * Q * s_n + s_t + (D + 1) * s_t) + wl.nodes
     k_ms = ms["collide"] / args.steps
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
     workload_key = f"d3q19_sphere_{args.size}_{args.precision}"
     traffic = measured_traffic(workload_key)
-    step_bytes = 4 * Q * s  # paper-state bytes per lattice update (N, B read + written)
+    # paper-state bytes per lattice update: N and B read once and written once
+    step_bytes = 4 * Q * s_n
+    # this implementation: colour kernel (N, phi_prev, record in; phi out) +
+    # fused kernel (N, phi in; N, record out)
+    impl_bytes = (Q * s_n + 2 * s_t + (D + 1) * s_t) + (2 * Q * s_n + s_t + (D + 1) * s_t)
     result = {
         "metric": "D3Q19 two-phase MLUPS & % HBM roofline",
         "value": round(mlups, 2),
@@ -152,7 +157,7 @@ def main() -> int:
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": "k_collide_stream", "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_ms": round(k_ms, 5)},
-        "step_roofline": {"bytes_per_update": step_bytes,
+        "step_roofline": {"bytes_per_update": step_bytes, "impl_bytes_per_update": impl_bytes,
                           "roofline_mlups": round(HBM_PEAK_GBS * 1e9 / step_bytes / 1e6, 1),
                           "frac": round(mlups / (HBM_PEAK_GBS * 1e9 / step_bytes / 1e6), 4)},
         "phase_ms_per_step": {k: round(v / args.steps, 5) for k, v in ms.items()},

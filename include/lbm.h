@@ -172,6 +172,36 @@ int lbm_read_field(lbm_ctx* ctx, int field, double* host_dst, size_t count);
  * 19 x 3 int32), *q_out = Q.  No context needed. */
 int lbm_lattice(uint32_t lattice, int32_t* c_out, int32_t* q_out);
 
+/* ---------------------------------------------------------------- batches
+ * Continuous batching of many runs: lbm_batch_step advances a set of started
+ * contexts of any sizes, lattices, precisions and angles with shared
+ * launches (per sub-step, one launch per phase for all contexts of the same
+ * lattice and precision; every workgroup looks its run up in a job table).
+ * Each context keeps its own buffer and state, so the set may change from
+ * one call to the next (runs join and leave between calls), and every run
+ * computes exactly what lbm_step would.  The job table lives in a device
+ * buffer the caller provides (no allocation in the library). */
+typedef struct lbm_batch lbm_batch;
+
+/* Device bytes of a job table for up to max_jobs contexts in one call. */
+int lbm_batch_table_bytes(int32_t max_jobs, size_t* bytes);
+
+/* Create a batch over a caller-owned, 256-byte aligned device table and the
+ * stream its launches go to.  Contexts passed to lbm_batch_step must be idle
+ * on their own streams or bound to this same stream. */
+int lbm_batch_create(void* device_table, size_t bytes, void* hip_stream, lbm_batch** out);
+
+/* Advance ctxs[j] by steps[j] >= 0 steps (count contexts, each at most
+ * once).  Waits for the batch stream's previous work first (the table is
+ * reused), then enqueues and returns; results appear like lbm_step's. */
+int lbm_batch_step(lbm_batch* batch, lbm_ctx* const* ctxs, const int64_t* steps, int32_t count);
+
+/* Release the batch (host memory only). */
+int lbm_batch_destroy(lbm_batch* batch);
+
+/* Last error of a batch call ("" if none). */
+const char* lbm_batch_last_error(const lbm_batch* batch);
+
 /* Release the context's host memory.  The device buffer stays the caller's. */
 int lbm_destroy(lbm_ctx* ctx);
 

@@ -258,10 +258,14 @@ static void equilibrium(const lattice_t* L, const double u[3], double p, double*
 /* Eq. 9 (this paper) or Eq. 10 (Fakhari et al.) ghost-node colour rule. */
 double orc_ghost_rule(double phiF, double eps, int rule) {
     if (rule == 0) return phiF / (phiF + (1.0 - phiF) * exp(eps));
-    /* Eq. 10 has a removable singularity at eps = 0 where it reduces to phiF. */
-    if (eps == 0.0) return phiF;
+    /* Eq. 10 has a removable singularity at eps = 0 (the paper notes it needs
+     * special care at 90 degrees).  With a = 1 + eps/2, multiplying
+     * (a - sqrt(a^2 - 2 eps phiF)) by its conjugate gives
+     * 2 eps phiF / (a + sqrt(a^2 - 2 eps phiF)); the factor eps cancels the
+     * 2/eps in front, leaving 4 phiF / (a + sqrt(...)) - phiF, which is the
+     * same function without the cancellation near eps = 0 (and phiF at 0). */
     double a = 1.0 + eps / 2.0;
-    return (2.0 / eps) * (a - sqrt(a * a - 2.0 * eps * phiF)) - phiF;
+    return 4.0 * phiF / (a + sqrt(a * a - 2.0 * eps * phiF)) - phiF;
 }
 
 /* Per-node macroscopic quantities shared by the step and the field readout. */

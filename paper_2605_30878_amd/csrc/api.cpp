@@ -3,6 +3,7 @@
 // of the caller's device buffer, and the C ABI of include/lbm.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -32,8 +33,9 @@ struct lbm_ctx {
     char* base = nullptr;
     hipStream_t stream = nullptr;
     DevState d{};
-    int cur = 0;   // population buffer holding the state
+    int cur = 0;   // population / compact-record buffer holding the state
     int ps = 0;    // phi buffer holding the solid values of the state
+    int from_planes = 1;  // liquid state in the B plane buffer (initial state, restore)
     int64_t step = 0;
     std::string err;
 };
@@ -66,6 +68,7 @@ static void lattice_table(int lattice, int& D, int& Q, int& NC, const int (**c)[
     }
 }
 
+// bytes of one stored population, and of every other per-node value
 static size_t elem_size(uint32_t prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 2); }
 static size_t phi_size(uint32_t prec) { return prec == LBM_FP64 ? 8 : 4; }
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
@@ -90,8 +93,7 @@ int lbm_create(const lbm_params* P, lbm_ctx** out) {
     *out = nullptr;
     if (P->abi_version != LBM_ABI_VERSION) return fail(nullptr, LBM_EINVAL, "abi_version mismatch");
     if (P->lattice != LBM_D2Q9 && P->lattice != LBM_D3Q19) return fail(nullptr, LBM_EINVAL, "unknown lattice");
-    if (P->precision != LBM_FP64 && P->precision != LBM_FP32)
-        return fail(nullptr, LBM_EINVAL, "precision not supported by this build");
+    if (P->precision > LBM_BF16_OFS) return fail(nullptr, LBM_EINVAL, "unknown precision");
     if (P->ghost_rule > LBM_GHOST_FAKHARI) return fail(nullptr, LBM_EINVAL, "unknown ghost rule");
     if (P->n[0] < 1 || P->n[1] < 1 || P->n[2] < 1) return fail(nullptr, LBM_EINVAL, "box sizes must be >= 1");
     if (P->lattice == LBM_D2Q9 && P->n[2] != 1) return fail(nullptr, LBM_EINVAL, "D2Q9 needs n[2] == 1");
@@ -113,8 +115,7 @@ int lbm_create(const lbm_params* P, lbm_ctx** out) {
     const double* w;
     lattice_table((int)P->lattice, c->D, c->Q, c->NC, &cv, &w);
     c->n = n;
-    c->S = (int64_t)align256((size_t)n * 8) / 8;   // plane stride: 256-byte aligned for FP64
-    if (P->precision != LBM_FP64) c->S = (int64_t)(align256((size_t)n * 4) / 4);
+    c->S = (n + 127) / 128 * 128;   // plane stride: planes of 2-, 4- and 8-byte values stay 256-byte aligned
     const double cs2 = 1.0 / 3.0;
     // Colour weights (Eq. A7): chi_0 = alpha, chi_i = (1 - alpha) w_i / (1 - w_0),
     // alpha from M_phi = (dt/2) [sum_i chi_i c_ix^2 + p] at p = 0.
@@ -307,9 +308,11 @@ int lbm_set_geometry(lbm_ctx* c, const lbm_solid* solids, int32_t count) {
     }
     // Device layout (all 256-byte aligned).
     const size_t es = elem_size(c->P.precision), fs = phi_size(c->P.precision);
-    const size_t plane = align256((size_t)c->S * es);
+    const size_t plane = align256((size_t)c->S * es), tplane = align256((size_t)c->S * fs);
     size_t off = 0;
-    off += 4 * (size_t)Q * plane;                       // N[2], B[2]
+    off += 2 * (size_t)Q * plane;                       // N[2]
+    off += (size_t)Q * tplane;                          // B
+    off += 2 * (size_t)(D + 1) * tplane;                // G[2]
     off += 2 * align256((size_t)c->S * fs);             // phi[2]
     off += align256((size_t)n);                         // flags
     off += align256((size_t)ng * 4);                    // g_node
@@ -349,11 +352,12 @@ int lbm_bind(lbm_ctx* c, void* dev, size_t bytes, void* stream) {
     const int Q = c->Q, NC = c->NC;
     const int64_t ng = (int64_t)c->g_node.size();
     const size_t es = elem_size(c->P.precision), fs = phi_size(c->P.precision);
-    const size_t plane = align256((size_t)c->S * es);
+    const size_t plane = align256((size_t)c->S * es), tplane = align256((size_t)c->S * fs);
     char* p = c->base;
     DevState& d = c->d;
     for (int b = 0; b < 2; b++) { d.N[b] = p; p += (size_t)Q * plane; }
-    for (int b = 0; b < 2; b++) { d.B[b] = p; p += (size_t)Q * plane; }
+    d.B = p; p += (size_t)Q * tplane;
+    for (int b = 0; b < 2; b++) { d.G[b] = p; p += (size_t)(c->D + 1) * tplane; }
     for (int b = 0; b < 2; b++) { d.phi[b] = p; p += align256((size_t)c->S * fs); }
     d.flags = (uint8_t*)p; p += align256((size_t)c->n);
     d.g_node = (int32_t*)p; p += align256((size_t)ng * 4);
@@ -431,6 +435,7 @@ int lbm_set_field(lbm_ctx* c, int field, const double* src, size_t count) {
         if ((rc = upload_aux(c, src, n, 0)) != LBM_OK) return rc;
         HIPCHK(c, launch_init(lat, prec, c->d, c->sp, c->cur, c->ps, c->stream), "init");
         HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
+        c->from_planes = 1;
         c->step = 0;
         c->started = true;
         return LBM_OK;
@@ -438,6 +443,15 @@ int lbm_set_field(lbm_ctx* c, int field, const double* src, size_t count) {
     case LBM_FIELD_B:
         if (!c->started) return fail(c, LBM_ESTATE, "set PHI first");
         if (count != (size_t)c->Q * n) return fail(c, LBM_EINVAL, "N/B need Q*n values");
+        if (!c->from_planes) {
+            // The compact liquid record depends on N: write B out to the
+            // plane buffer first so that it keeps its value.
+            for (int i = 0; i < c->Q; i++) {
+                HIPCHK(c, launch_plane_out(lat, prec, c->d, c->sp, 1, i, c->cur, c->ps, 0, c->stream), "B out");
+                HIPCHK(c, launch_plane_in(lat, prec, c->d, c->sp, 1, i, c->cur, c->stream), "B in");
+            }
+            c->from_planes = 1;
+        }
         for (int i = 0; i < c->Q; i++) {
             if ((rc = upload_aux(c, src + (size_t)i * n, n, 0)) != LBM_OK) return rc;
             HIPCHK(c, launch_plane_in(lat, prec, c->d, c->sp, field == LBM_FIELD_N ? 0 : 1, i, c->cur, c->stream),
@@ -450,7 +464,6 @@ int lbm_set_field(lbm_ctx* c, int field, const double* src, size_t count) {
         if (count != (size_t)n) return fail(c, LBM_EINVAL, "SOLID_PHI needs n values");
         if ((rc = upload_aux(c, src, n, 0)) != LBM_OK) return rc;
         HIPCHK(c, launch_plane_in(lat, prec, c->d, c->sp, 2, 0, c->cur, c->stream), "plane in");
-        HIPCHK(c, launch_plane_in(lat, prec, c->d, c->sp, 2, 1, c->cur, c->stream), "plane in");
         HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
         return LBM_OK;
     default:
@@ -463,10 +476,12 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
     if (!c->started) return fail(c, LBM_ESTATE, "set PHI before stepping");
     if (nsteps < 0) return fail(c, LBM_EINVAL, "nsteps must be >= 0");
     for (int64_t k = 0; k < nsteps; k++) {
-        hipError_t e = launch_step((int)c->P.lattice, c->P.precision, c->d, c->sp, c->cur, c->ps, c->stream);
+        hipError_t e = launch_step((int)c->P.lattice, c->P.precision, c->d, c->sp, c->cur, c->ps, c->from_planes,
+                                   c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "step launch");
         c->cur ^= 1;
         c->ps ^= 1;
+        c->from_planes = 0;
         c->step++;
     }
     return LBM_OK;
@@ -487,12 +502,14 @@ int lbm_step_profiled(lbm_ctx* c, int64_t nsteps, double* ms_out) {
         hipEvent_t* E = &ev[(size_t)s * (NPH + 1)];
         hipError_t e = hipEventRecord(E[0], c->stream);
         for (int ph = 0; ph < NPH && e == hipSuccess; ph++) {
-            e = launch_phase((int)c->P.lattice, c->P.precision, ph, c->d, c->sp, c->cur, c->ps, c->stream);
+            e = launch_phase((int)c->P.lattice, c->P.precision, ph, c->d, c->sp, c->cur, c->ps, c->from_planes,
+                             c->stream);
             if (e == hipSuccess) e = hipEventRecord(E[ph + 1], c->stream);
         }
         if (e != hipSuccess) { rc = hip_fail(c, e, "profiled step"); break; }
         c->cur ^= 1;
         c->ps ^= 1;
+        c->from_planes = 0;
         c->step++;
     }
     if (rc == LBM_OK) {
@@ -526,9 +543,9 @@ int lbm_observe(lbm_ctx* c, lbm_obs* out) {
     if (!c->started) return fail(c, LBM_ESTATE, "set PHI before observing");
     const int lat = (int)c->P.lattice;
     const uint32_t prec = c->P.precision;
-    HIPCHK(c, launch_colour(lat, prec, c->d, c->sp, c->cur, c->ps, c->stream), "colour");
+    HIPCHK(c, launch_colour(lat, prec, c->d, c->sp, c->cur, c->ps, c->from_planes, c->stream), "colour");
     HIPCHK(c, launch_macro(lat, prec, c->d, c->sp, c->cur, c->ps, c->stream), "macro");
-    HIPCHK(c, launch_reduce(lat, prec, c->d, c->sp, c->cur, c->ps, c->stream), "reduce");
+    HIPCHK(c, launch_reduce(lat, prec, c->d, c->sp, c->cur, c->ps, c->from_planes, c->stream), "reduce");
     double r[8];
     int64_t nf = 0;
     HIPCHK(c, hipMemcpyAsync(r, c->d.result, 8 * 8, hipMemcpyDeviceToHost, c->stream), "download");
@@ -574,17 +591,19 @@ int lbm_read_field(lbm_ctx* c, int field, double* dst, size_t count) {
     switch (field) {
     case LBM_FIELD_PHI:
         if (count != (size_t)n) return fail(c, LBM_EINVAL, "PHI has n values");
-        HIPCHK(c, launch_colour(lat, prec, c->d, c->sp, c->cur, c->ps, c->stream), "colour");
-        HIPCHK(c, launch_plane_out(lat, prec, c->d, c->sp, 2, 1 - c->ps, c->cur, c->stream), "plane out");
+        HIPCHK(c, launch_colour(lat, prec, c->d, c->sp, c->cur, c->ps, c->from_planes, c->stream), "colour");
+        HIPCHK(c, launch_plane_out(lat, prec, c->d, c->sp, 2, 1 - c->ps, c->cur, c->ps, c->from_planes, c->stream),
+               "plane out");
         return download(c, dst, c->d.aux, n);
     case LBM_FIELD_SOLID_PHI:
         if (count != (size_t)n) return fail(c, LBM_EINVAL, "SOLID_PHI has n values");
-        HIPCHK(c, launch_plane_out(lat, prec, c->d, c->sp, 2, c->ps, c->cur, c->stream), "plane out");
+        HIPCHK(c, launch_plane_out(lat, prec, c->d, c->sp, 2, c->ps, c->cur, c->ps, c->from_planes, c->stream),
+               "plane out");
         return download(c, dst, c->d.aux, n);
     case LBM_FIELD_U:
     case LBM_FIELD_P:
         if (count != (size_t)(field == LBM_FIELD_U ? 3 * n : n)) return fail(c, LBM_EINVAL, "wrong count");
-        HIPCHK(c, launch_colour(lat, prec, c->d, c->sp, c->cur, c->ps, c->stream), "colour");
+        HIPCHK(c, launch_colour(lat, prec, c->d, c->sp, c->cur, c->ps, c->from_planes, c->stream), "colour");
         HIPCHK(c, launch_macro(lat, prec, c->d, c->sp, c->cur, c->ps, c->stream), "macro");
         if (field == LBM_FIELD_P) return download(c, dst, c->d.aux + 3 * c->S, n);
         for (int a = 0; a < 3; a++)
@@ -594,7 +613,8 @@ int lbm_read_field(lbm_ctx* c, int field, double* dst, size_t count) {
     case LBM_FIELD_B:
         if (count != (size_t)c->Q * n) return fail(c, LBM_EINVAL, "N/B have Q*n values");
         for (int i = 0; i < c->Q; i++) {
-            HIPCHK(c, launch_plane_out(lat, prec, c->d, c->sp, field == LBM_FIELD_N ? 0 : 1, i, c->cur, c->stream),
+            HIPCHK(c, launch_plane_out(lat, prec, c->d, c->sp, field == LBM_FIELD_N ? 0 : 1, i, c->cur, c->ps,
+                                       c->from_planes, c->stream),
                    "plane out");
             if ((rc = download(c, dst + (size_t)i * n, c->d.aux, n)) != LBM_OK) return rc;
         }
@@ -602,6 +622,121 @@ int lbm_read_field(lbm_ctx* c, int field, double* dst, size_t count) {
     default:
         return fail(c, LBM_EINVAL, "unknown field");
     }
+}
+
+// ------------------------------------------------------------------ batches
+struct lbm_batch {
+    char* table = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    std::vector<char> staging[4];
+    std::string err;
+};
+
+static int bfail(lbm_batch* b, int code, const std::string& msg) {
+    if (b) b->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+int lbm_batch_table_bytes(int32_t max_jobs, size_t* bytes) {
+    if (!bytes || max_jobs < 1) return LBM_EINVAL;
+    *bytes = batch_table_bytes(max_jobs);
+    return LBM_OK;
+}
+
+int lbm_batch_create(void* device_table, size_t bytes, void* hip_stream, lbm_batch** out) {
+    if (!out) return bfail(nullptr, LBM_EINVAL, "null argument");
+    *out = nullptr;
+    if (!device_table) return bfail(nullptr, LBM_EINVAL, "null device table");
+    if (((uintptr_t)device_table) & 255u) return bfail(nullptr, LBM_EINVAL, "device table must be 256-byte aligned");
+    if (bytes < batch_table_bytes(1)) return bfail(nullptr, LBM_ENOMEM, "device table too small");
+    lbm_batch* b = new (std::nothrow) lbm_batch();
+    if (!b) return bfail(nullptr, LBM_ENOMEM, "host allocation failed");
+    b->table = (char*)device_table;
+    b->bytes = bytes;
+    b->stream = (hipStream_t)hip_stream;
+    *out = b;
+    return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch* b, lbm_ctx* const* ctxs, const int64_t* steps, int32_t count) {
+    if (!b) return LBM_EINVAL;
+    if (count < 0 || (count > 0 && (!ctxs || !steps))) return bfail(b, LBM_EINVAL, "bad job list");
+    if (count == 0) return LBM_OK;
+    for (int32_t j = 0; j < count; j++) {
+        if (!ctxs[j]) return bfail(b, LBM_EINVAL, "null context");
+        if (!ctxs[j]->started) return bfail(b, LBM_ESTATE, "every context must be started (PHI set)");
+        if (steps[j] < 0) return bfail(b, LBM_EINVAL, "steps must be >= 0");
+        for (int32_t k = 0; k < j; k++)
+            if (ctxs[k] == ctxs[j]) return bfail(b, LBM_EINVAL, "a context appears twice");
+    }
+    // The staging buffers of the previous call must have reached the device.
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return bfail(b, LBM_EHIP, std::string("sync: ") + hipGetErrorString(e));
+    size_t off = 0;
+    int group = 0;
+    for (uint32_t lat = 0; lat < 2; lat++) {
+        for (uint32_t prec = 0; prec < 4; prec++) {
+            std::vector<BatchJobHost> jobs;
+            std::vector<lbm_ctx*> who;
+            for (int32_t j = 0; j < count; j++) {
+                lbm_ctx* c = ctxs[j];
+                if (c->P.lattice != lat || c->P.precision != prec || steps[j] == 0) continue;
+                BatchJobHost h;
+                h.d = c->d;
+                h.p = c->sp;
+                h.cur0 = c->cur;
+                h.ps0 = c->ps;
+                h.planes0 = c->from_planes;
+                h.steps = steps[j];
+                jobs.push_back(h);
+                who.push_back(c);
+            }
+            if (jobs.empty()) continue;
+            std::vector<size_t> order(jobs.size());
+            for (size_t k = 0; k < order.size(); k++) order[k] = k;
+            std::stable_sort(order.begin(), order.end(),
+                             [&](size_t a, size_t c) { return jobs[a].steps > jobs[c].steps; });
+            std::vector<BatchJobHost> sorted;
+            int64_t nsteps = 0;
+            for (size_t k : order) {
+                sorted.push_back(jobs[k]);
+                nsteps = std::max(nsteps, jobs[k].steps);
+            }
+            const size_t need = batch_table_bytes((int)sorted.size());
+            if (off + need > b->bytes) return bfail(b, LBM_ENOMEM, "batch table too small for this many jobs");
+            e = launch_batch((int)lat, prec, sorted.data(), (int)sorted.size(), b->table + off, need, nsteps, b->stream,
+                             b->staging[group & 3]);
+            if (e != hipSuccess) return bfail(b, LBM_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
+            off += need;
+            group++;
+            for (size_t k = 0; k < who.size(); k++) {
+                lbm_ctx* c = who[k];
+                const int64_t n = jobs[k].steps;
+                if (n & 1) {
+                    c->cur ^= 1;
+                    c->ps ^= 1;
+                }
+                c->from_planes = 0;
+                c->step += n;
+            }
+        }
+    }
+    if (group > 4) return bfail(b, LBM_EINVAL, "internal: more than four groups");
+    return LBM_OK;
+}
+
+int lbm_batch_destroy(lbm_batch* b) {
+    if (!b) return LBM_EINVAL;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    delete b;
+    return LBM_OK;
+}
+
+const char* lbm_batch_last_error(const lbm_batch* b) {
+    if (!b) return g_create_error.c_str();
+    return b->err.c_str();
 }
 
 int lbm_destroy(lbm_ctx* c) {

@@ -2,18 +2,32 @@
 // Boltzmann time step with the ghost-node wetting condition.
 //
 // Per step, on one stream:
-//   k_colour   phi = sum_i B_i at fluid nodes                      (Eq. A13)
-//   k_ghost    phi_G = phi_F / (phi_F + (1 - phi_F) exp(eps))      (Eq. 9)
-//              over the compacted ghost list; phi_F interpolated at
-//              x_F = x_G + n_s from one snapshot (Jacobi)
-//   k_collide  fused: colour stencils, forces (Eq. 4, A9-A11), MRT
-//              collision (Eq. A1) in projection form, recolouring (Eq. A12),
-//              push streaming of N and B (Eq. A16-A17) with halfway
-//              bounce-back at solid links
+//   k_colour_*  phi = sum_i B_i at fluid nodes                      (Eq. A13)
+//   k_ghost     phi_G = phi_F / (phi_F + (1 - phi_F) exp(eps))      (Eq. 9)
+//               over the compacted ghost list; phi_F interpolated at
+//               x_F = x_G + n_s from one snapshot (Jacobi)
+//   k_collide   fused: colour stencils, forces (Eq. 4, A9-A11), MRT
+//               collision (Eq. A1) in projection form, recolouring
+//               (Eq. A12), push streaming (Eq. A16-A17) with halfway
+//               bounce-back at solid links
+//
+// Liquid populations in compact form.  The recolouring of Eq. A12 is
+//   B*_i(x) = phi(x) N*_i(x) + (c_i . G(x)) N^eq_i(u = 0, p(x)),
+//   G = (2/W) max(phi (1 - phi), 0) n_phi,  N^eq_i(0, p) = chi_i + w_i p / cs^2,
+// and streaming moves B*_i(x) to x + c_i exactly as it moves N*_i(x).  So the
+// post-stream B_i(y) is fixed by the post-stream N_i(y) and three fields of
+// the previous step at the source node y - c_i: phi, G and p.  The fused
+// kernel stores G and p (D + 1 values per node) instead of Q streamed B
+// planes, and the colour kernel forms B_i(y) from them on the fly.  At a
+// bounce-back link the source is y itself with c_i reversed.  This is the
+// same arithmetic as storing B (up to rounding); the Q-plane B buffer is only
+// read right after the initial state or a restore.
+//
 // Populations are SoA planes [Q][S], double-buffered; phi is double-buffered
 // so that the ghost update reads last step's solid values while writing the
-// new ones.  Every step is HBM-bound (about 4 Q s bytes per fluid node);
-// nothing is a dense contraction, so no MFMA is used.
+// new ones, and the previous step's phi at fluid nodes stays available for
+// the compact B.  Every kernel is HBM-bound; nothing is a dense contraction,
+// so no MFMA is used.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -22,6 +36,10 @@
 
 #include "lattice.h"
 #include "launch.h"
+
+#ifndef LBM_COLLIDE_BX
+#define LBM_COLLIDE_BX 256   // threads per row block of the fused kernel
+#endif
 
 namespace lbm {
 
@@ -42,6 +60,35 @@ __device__ __forceinline__ T cmul(T v) {
     else return T(0);
 }
 
+// Storage of the colour-blind populations.  FP64 / FP32 runs store the
+// value itself.  16-bit runs store the offset from the rest state,
+// h_i = (N_i - chi_i) / s with a power-of-two scale s (FP16 or BF16, rounded
+// to nearest even), so N_i = chi_i + s h_i; arithmetic stays FP32.
+// The rest population closes the zeroth moment of the stored values:
+// sum_i N*_i = 1 exactly in the model (Eq. A4 sums to 1 and the forcing has no
+// zeroth moment), so N*_0 is written as the closure of the other Q - 1
+// stored values ("off" space: the value itself, or the 16-bit offset).
+template <class T, class SN>
+struct NStore {
+    static constexpr bool offset = false;
+    __device__ __forceinline__ static T dec(SN h, T, T) { return h; }
+    __device__ __forceinline__ static SN enc(T v, T, T) { return v; }
+    __device__ __forceinline__ static T off(SN h) { return h; }
+    __device__ __forceinline__ static SN enc_off(T o) { return o; }
+};
+template <class SN>
+struct NStore16 {
+    static constexpr bool offset = true;
+    __device__ __forceinline__ static float dec(SN h, float chi, float s) { return chi + s * (float)h; }
+    __device__ __forceinline__ static SN enc(float v, float chi, float inv_s) { return (SN)((v - chi) * inv_s); }
+    __device__ __forceinline__ static float off(SN h) { return (float)h; }
+    __device__ __forceinline__ static SN enc_off(float o) { return (SN)o; }
+};
+template <>
+struct NStore<float, _Float16> : NStore16<_Float16> {};
+template <>
+struct NStore<float, __bf16> : NStore16<__bf16> {};
+
 // Arithmetic-type constants of a run.
 template <class T, int Q>
 struct KParams {
@@ -52,11 +99,17 @@ struct KParams {
     T chi[Q];
     T chi0;
     T n_thresh2;            // |grad phi|^2 below which n_phi = 0
+    T n_s, n_inv_s;         // 16-bit storage scale of N and its inverse
+    T n_close;              // target of the closure sum in "off" space
     int nx, ny, nz;
     int64_t S;
 };
 
-template <class T, class L>
+// Scale of the 16-bit offsets: 2^-10 keeps offsets of 1e-5 .. 1e-2 (the
+// range near the rest state) in FP16's normal range.
+constexpr double N16_SCALE = 1.0 / 1024.0;
+
+template <class T, class L, class SN>
 static KParams<T, L::Q> make_kparams(const StepParams& p) {
     KParams<T, L::Q> k;
     k.rho_g = T(p.rho_g);
@@ -71,12 +124,30 @@ static KParams<T, L::Q> make_kparams(const StepParams& p) {
     k.chi0 = T(p.chi0);
     // |grad phi| > 1e-12 (FP64) or > 1e-7 (FP32) defines the interface normal
     k.n_thresh2 = std::is_same<T, double>::value ? T(1e-24) : T(1e-14);
+    if (NStore<T, SN>::offset) {
+        double sum_chi = 0.0;
+        for (int i = 0; i < L::Q; i++) sum_chi += (double)k.chi[i];
+        k.n_s = T(N16_SCALE);
+        k.n_inv_s = T(1.0 / N16_SCALE);
+        k.n_close = T((1.0 - sum_chi) / N16_SCALE);
+    } else {
+        k.n_s = T(1);
+        k.n_inv_s = T(1);
+        k.n_close = T(1);
+    }
     k.nx = p.nx;
     k.ny = p.ny;
     k.nz = p.nz;
     k.S = p.S;
     return k;
 }
+
+// Planes of the compact liquid record: G (D components) then p.
+template <class L>
+struct GRec {
+    static constexpr int K = L::D + 1;
+    static constexpr int P = L::D;   // plane index of p
+};
 
 // Node output of the macroscopic stage.
 template <class T>
@@ -178,11 +249,12 @@ __device__ __forceinline__ void macro_stage(const T (&N)[L::Q], const T (&ph)[L:
 
 // Collision in projection form, exactly equal to Eq. A1 with S relaxing the
 // traceless second moments at 1/tau and every other moment at 1:
-//   N* = N^eq(u, p) + F/2 + (1 - 1/tau) P_sigma (N - N^eq(u, p)),
-// then recolouring (Eq. A12) with the amplitude max(phi(1 - phi), 0).
+//   N* = N^eq(u, p) + F/2 + (1 - 1/tau) P_sigma (N - N^eq(u, p)).
+// Also returns the recolouring vector G = (2/W) max(phi(1 - phi), 0) n_phi
+// of Eq. A12.
 template <class L, class T>
 __device__ __forceinline__ void collide_stage(const Macro<T>& m, const T (&Pi)[6], const KParams<T, L::Q>& P,
-                                              T (&Ns)[L::Q], T (&Bs)[L::Q]) {
+                                              T (&Ns)[L::Q], T (&G)[3]) {
     constexpr int Q = L::Q;
     constexpr T w0 = T(L::w[0]);
     const T ux = m.u[0], uy = m.u[1], uz = m.u[2];
@@ -203,32 +275,8 @@ __device__ __forceinline__ void collide_stage(const Macro<T>& m, const T (&Pi)[6
         s4 = omega * (Pi[4] - uy * uz) * T(0.25);
         s5 = omega * (Pi[5] - ux * uz) * T(0.25);
     }
-    // Recolouring normal and amplitude.
-    const T gx = m.grad[0], gy = m.grad[1], gz = m.grad[2];
-    const T gn2 = gx * gx + gy * gy + gz * gz;
-    T nx = 0, ny = 0, nz = 0;
-    if (gn2 > P.n_thresh2) {
-        const T inv = T(1) / sqrt(gn2);
-        nx = gx * inv;
-        ny = gy * inv;
-        nz = gz * inv;
-    }
-    T amp = m.phi * (T(1) - m.phi);
-    amp = amp > T(0) ? amp : T(0);
-    const T kseg = T(2) * P.inv_W * amp;
-    const T phi = m.phi;
-    // i = 0
-    {
-        const T neq = P.chi[0] - (T(1) - w0) * p3 - w0 * T(1.5) * uu;
-        T proj = 0;
-        if constexpr (L::D == 2) {
-            proj = 0;  // rest direction has zero stress moments
-        } else {
-            proj = 0;
-        }
-        Ns[0] = neq + omega * proj;
-        Bs[0] = phi * Ns[0];
-    }
+    // The rest direction has no stress moment.
+    Ns[0] = P.chi[0] - (T(1) - w0) * p3 - w0 * T(1.5) * uu;
     static_for<1, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
@@ -244,12 +292,21 @@ __device__ __forceinline__ void collide_stage(const Macro<T>& m, const T (&Pi)[6
             proj = T(2 * cx * cx - cy * cy - cz * cz) * s1 + T(cy * cy - cz * cz) * s2 + T(cx * cy) * s3 +
                    T(cy * cz) * s4 + T(cx * cz) * s5;
         }
-        const T ns = neq + T(1.5) * wi * ca + proj;   // F_i / 2 = (3 w_i a.c_i) / 2
-        Ns[i] = ns;
-        const T cn = cmul<cx>(nx) + cmul<cy>(ny) + cmul<cz>(nz);
-        const T neq0 = P.chi[i] + wi * p3;            // N^eq(u = 0, p), i != 0
-        Bs[i] = phi * ns + kseg * cn * neq0;
+        Ns[i] = neq + T(1.5) * wi * ca + proj;   // F_i / 2 = (3 w_i a.c_i) / 2
     });
+    // Recolouring vector: normal where |grad phi| is resolved, amplitude
+    // clamped at 0 where phi leaves [0, 1].
+    const T gx = m.grad[0], gy = m.grad[1], gz = m.grad[2];
+    const T gn2 = gx * gx + gy * gy + gz * gz;
+    T amp = m.phi * (T(1) - m.phi);
+    amp = amp > T(0) ? amp : T(0);
+    G[0] = G[1] = G[2] = T(0);
+    if (gn2 > P.n_thresh2) {
+        const T k = T(2) * P.inv_W * amp / sqrt(gn2);
+        G[0] = k * gx;
+        G[1] = k * gy;
+        G[2] = k * gz;
+    }
 }
 
 // Neighbour index tables of a node: nb[i] = index of x + c_i (periodic).
@@ -273,12 +330,56 @@ __device__ __forceinline__ void neighbours(int ix, int iy, int iz, int nx, int n
 }
 
 // ------------------------------------------------------------------ kernels
-// phi = sum_i B_i (i ascending) at fluid nodes.
+// Row decomposition shared by the stencil kernels: grid (x-blocks, ny, nz).
+struct RowIdx {
+    int ix, iy, iz;
+    int64_t x;
+};
+
+__device__ __forceinline__ bool row_index(int nx, int ny, RowIdx& r) {
+    r.ix = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r.ix >= nx) return false;
+    r.iy = blockIdx.y;
+    r.iz = blockIdx.z;
+    r.x = (int64_t)r.ix + (int64_t)nx * ((int64_t)r.iy + (int64_t)ny * r.iz);
+    return true;
+}
+
+// Post-stream liquid population B_i(y) from the compact record.  nb[i] is
+// y + c_i, so the source y - c_i is nb[opp(i)]; at a bounce-back link the
+// source is y with c_i reversed.
+template <class L, class T, class SN, int I>
+__device__ __forceinline__ T compact_B(const SN* __restrict__ N, const T* __restrict__ phi_prev,
+                                       const T* __restrict__ G, const uint8_t* __restrict__ flags,
+                                       const KParams<T, L::Q>& P, int64_t y, const int64_t (&nb)[L::Q],
+                                       bool near_solid) {
+    const int64_t S = P.S;
+    const T n = NStore<T, SN>::dec(N[(int64_t)I * S + y], P.chi[I], P.n_s);
+    if constexpr (I == 0) {
+        return phi_prev[y] * n;
+    } else {
+        constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
+        constexpr T wi = T(L::w[I]);
+        int64_t src = nb[L::opp[I]];
+        T sgn = T(1);
+        if (near_solid && (flags[src] & FLAG_SOLID)) {
+            src = y;
+            sgn = T(-1);
+        }
+        T cG = T(0);
+        if constexpr (cx != 0) cG += cmul<cx>(G[src]);
+        if constexpr (cy != 0) cG += cmul<cy>(G[S + src]);
+        if constexpr (cz != 0) cG += cmul<cz>(G[2 * S + src]);
+        const T p = G[(int64_t)GRec<L>::P * S + src];
+        return phi_prev[src] * n + sgn * cG * (P.chi[I] + wi * T(3) * p);
+    }
+}
+
+// phi = sum_i B_i (i ascending) from the Q-plane B buffer (initial state or
+// a restore).
 template <class L, class T>
-__global__ __launch_bounds__(256) void k_colour(const T* __restrict__ B, T* __restrict__ phi,
-                                                const uint8_t* __restrict__ flags, int64_t n, int64_t S) {
-    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= n) return;
+__device__ __forceinline__ void colour_planes_node(const T* __restrict__ B, T* __restrict__ phi,
+                                                   const uint8_t* __restrict__ flags, int64_t x, int64_t S) {
     if (flags[x] & FLAG_SOLID) return;
     T acc = 0;
 #pragma unroll
@@ -286,15 +387,74 @@ __global__ __launch_bounds__(256) void k_colour(const T* __restrict__ B, T* __re
     phi[x] = acc;
 }
 
+template <class L, class T>
+__global__ __launch_bounds__(256) void k_colour_planes(const T* __restrict__ B, T* __restrict__ phi,
+                                                       const uint8_t* __restrict__ flags, int64_t n, int64_t S) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    colour_planes_node<L, T>(B, phi, flags, x, S);
+}
+
+// phi = sum_i B_i (i ascending) with B_i formed from the compact record,
+// one node.
+template <class L, class T, class SN>
+__device__ __forceinline__ void colour_compact_node(const SN* __restrict__ N, const T* __restrict__ phi_prev,
+                                                    const T* __restrict__ G, const uint8_t* __restrict__ flags,
+                                                    T* __restrict__ phi, const KParams<T, L::Q>& P, int ix, int iy,
+                                                    int iz) {
+    const int64_t x = (int64_t)ix + (int64_t)P.nx * ((int64_t)iy + (int64_t)P.ny * iz);
+    const uint8_t f = flags[x];
+    if (f & FLAG_SOLID) return;
+    int64_t nb[L::Q];
+    neighbours<L>(ix, iy, iz, P.nx, P.ny, P.nz, nb);
+    const bool near = (f & FLAG_NEAR_SOLID) != 0;
+    T acc = 0;
+    static_for<0, L::Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        acc += compact_B<L, T, SN, i>(N, phi_prev, G, flags, P, x, nb, near);
+    });
+    phi[x] = acc;
+}
+
+template <class L, class T, class SN>
+__global__ __launch_bounds__(256) void k_colour_compact(const SN* __restrict__ N, const T* __restrict__ phi_prev,
+                                                        const T* __restrict__ G, const uint8_t* __restrict__ flags,
+                                                        T* __restrict__ phi, KParams<T, L::Q> P) {
+    RowIdx r;
+    if (!row_index(P.nx, P.ny, r)) return;
+    colour_compact_node<L, T, SN>(N, phi_prev, G, flags, phi, P, r.ix, r.iy, r.iz);
+}
+
+// One direction plane of B from the compact record into FP64 (read-out).
+template <class L, class T, class SN>
+__global__ __launch_bounds__(256) void k_compact_B_plane(const SN* __restrict__ N, const T* __restrict__ phi_prev,
+                                                         const T* __restrict__ G, const uint8_t* __restrict__ flags,
+                                                         KParams<T, L::Q> P, int dir, double* __restrict__ out) {
+    RowIdx r;
+    if (!row_index(P.nx, P.ny, r)) return;
+    const uint8_t f = flags[r.x];
+    if (f & FLAG_SOLID) {
+        out[r.x] = 0.0;
+        return;
+    }
+    int64_t nb[L::Q];
+    neighbours<L>(r.ix, r.iy, r.iz, P.nx, P.ny, P.nz, nb);
+    const bool near = (f & FLAG_NEAR_SOLID) != 0;
+    T v = 0;
+    static_for<0, L::Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if (i == dir) v = compact_B<L, T, SN, i>(N, phi_prev, G, flags, P, r.x, nb, near);
+    });
+    out[r.x] = (double)v;
+}
+
 // Ghost update over the compacted list (Jacobi): fluid corners from the
 // colour field just written, solid corners from last step's values.
 template <class T, int NC>
-__global__ __launch_bounds__(256) void k_ghost(const int32_t* __restrict__ g_node, const int32_t* __restrict__ g_corner,
-                                               const T* __restrict__ g_w, const uint8_t* __restrict__ g_mask, int ng,
-                                               const T* __restrict__ phi_prev, T* __restrict__ phi_work, T E, T eps,
-                                               int rule) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ng) return;
+__device__ __forceinline__ void ghost_one(const int32_t* __restrict__ g_node, const int32_t* __restrict__ g_corner,
+                                          const T* __restrict__ g_w, const uint8_t* __restrict__ g_mask, int ng,
+                                          const T* __restrict__ phi_prev, T* __restrict__ phi_work, T E, T eps,
+                                          int rule, int g) {
     const uint32_t mask = g_mask[g];
     T f = 0;
 #pragma unroll
@@ -306,71 +466,95 @@ __global__ __launch_bounds__(256) void k_ghost(const int32_t* __restrict__ g_nod
     T out;
     if (rule == 0) {
         out = f / (f + (T(1) - f) * E);                    // Eq. 9
-    } else if (eps == T(0)) {
-        out = f;                                           // Eq. 10 at its removable singularity
     } else {
-        const T a = T(1) + T(0.5) * eps;                   // Eq. 10
-        out = (T(2) / eps) * (a - sqrt(a * a - T(2) * eps * f)) - f;
+        // Eq. 10, rationalised: (2/eps)(a - r) = 4 f / (a + r) with
+        // a = 1 + eps/2, r = sqrt(a^2 - 2 eps f); no 0/0 at eps = 0.
+        const T a = T(1) + T(0.5) * eps;
+        out = T(4) * f / (a + sqrt(a * a - T(2) * eps * f)) - f;
     }
     phi_work[g_node[g]] = out;
 }
 
+template <class T, int NC>
+__global__ __launch_bounds__(256) void k_ghost(const int32_t* __restrict__ g_node, const int32_t* __restrict__ g_corner,
+                                               const T* __restrict__ g_w, const uint8_t* __restrict__ g_mask, int ng,
+                                               const T* __restrict__ phi_prev, T* __restrict__ phi_work, T E, T eps,
+                                               int rule) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ng) return;
+    ghost_one<T, NC>(g_node, g_corner, g_w, g_mask, ng, phi_prev, phi_work, E, eps, rule, g);
+}
+
 // Fused stencil + forces + collision + recolouring + push streaming with
-// halfway bounce-back.  One thread per node of an x-row; grid (x-blocks, ny, nz).
-template <class L, class T>
-__global__ __launch_bounds__(256) void k_collide_stream(const T* __restrict__ Nsrc, T* __restrict__ Ndst,
-                                                        T* __restrict__ Bdst, const T* __restrict__ phi,
-                                                        const uint8_t* __restrict__ flags, KParams<T, L::Q> P) {
+// halfway bounce-back, one node.  Writes the streamed N* and the node's
+// compact liquid record (G, p).
+template <class L, class T, class SN>
+__device__ __forceinline__ void collide_node(const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
+                                             T* __restrict__ Gdst, const T* __restrict__ phi,
+                                             const uint8_t* __restrict__ flags, const KParams<T, L::Q>& P, int ix,
+                                             int iy, int iz) {
     constexpr int Q = L::Q;
-    const int ix = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ix >= P.nx) return;
-    const int iy = blockIdx.y, iz = blockIdx.z;
     const int64_t x = (int64_t)ix + (int64_t)P.nx * ((int64_t)iy + (int64_t)P.ny * iz);
     const uint8_t f = flags[x];
     if (f & FLAG_SOLID) return;
     int64_t nb[Q];
     neighbours<L>(ix, iy, iz, P.nx, P.ny, P.nz, nb);
+    using NS = NStore<T, SN>;
     T N[Q], ph[Q];
 #pragma unroll
-    for (int i = 0; i < Q; i++) N[i] = Nsrc[(int64_t)i * P.S + x];
+    for (int i = 0; i < Q; i++) N[i] = NS::dec(Nsrc[(int64_t)i * P.S + x], P.chi[i], P.n_s);
 #pragma unroll
     for (int i = 0; i < Q; i++) ph[i] = phi[nb[i]];
     Macro<T> m;
     T Pi[6];
     macro_stage<L, T>(N, ph, P, m, Pi);
-    T Ns[Q], Bs[Q];
-    collide_stage<L, T>(m, Pi, P, Ns, Bs);
+    T Ns[Q], G[3];
+    collide_stage<L, T>(m, Pi, P, Ns, G);
+    // Encode for storage; the rest population closes the stored zeroth moment.
+    SN e[Q];
+    T closure = P.n_close;
+#pragma unroll
+    for (int i = 1; i < Q; i++) {
+        e[i] = NS::enc(Ns[i], P.chi[i], P.n_inv_s);
+        closure -= NS::off(e[i]);
+    }
+    e[0] = NS::enc_off(closure);
     const int64_t S = P.S;
     if (f & FLAG_NEAR_SOLID) {
         static_for<0, Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            if (flags[nb[i]] & FLAG_SOLID) {
-                Ndst[(int64_t)L::opp[i] * S + x] = Ns[i];
-                Bdst[(int64_t)L::opp[i] * S + x] = Bs[i];
-            } else {
-                Ndst[(int64_t)i * S + nb[i]] = Ns[i];
-                Bdst[(int64_t)i * S + nb[i]] = Bs[i];
-            }
+            if (flags[nb[i]] & FLAG_SOLID) Ndst[(int64_t)L::opp[i] * S + x] = e[i];
+            else Ndst[(int64_t)i * S + nb[i]] = e[i];
         });
     } else {
 #pragma unroll
-        for (int i = 0; i < Q; i++) {
-            Ndst[(int64_t)i * S + nb[i]] = Ns[i];
-            Bdst[(int64_t)i * S + nb[i]] = Bs[i];
-        }
+        for (int i = 0; i < Q; i++) Ndst[(int64_t)i * S + nb[i]] = e[i];
     }
+#pragma unroll
+    for (int a = 0; a < L::D; a++) Gdst[(int64_t)a * S + x] = G[a];
+    Gdst[(int64_t)GRec<L>::P * S + x] = m.p;
+}
+
+// One thread per node of an x-row; grid (x-blocks, ny, nz).
+template <class L, class T, class SN>
+__global__ __launch_bounds__(LBM_COLLIDE_BX) void k_collide_stream(const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
+                                                                   T* __restrict__ Gdst, const T* __restrict__ phi,
+                                                                   const uint8_t* __restrict__ flags,
+                                                                   KParams<T, L::Q> P) {
+    RowIdx r;
+    if (!row_index(P.nx, P.ny, r)) return;
+    collide_node<L, T, SN>(Nsrc, Ndst, Gdst, phi, flags, P, r.ix, r.iy, r.iz);
 }
 
 // Macroscopic fields (u, p) of every node into FP64 planes; solids get 0.
-template <class L, class T>
-__global__ __launch_bounds__(256) void k_macro(const T* __restrict__ Nsrc, const T* __restrict__ phi,
+template <class L, class T, class SN>
+__global__ __launch_bounds__(256) void k_macro(const SN* __restrict__ Nsrc, const T* __restrict__ phi,
                                                const uint8_t* __restrict__ flags, KParams<T, L::Q> P,
                                                double* __restrict__ aux) {
     constexpr int Q = L::Q;
-    const int ix = blockIdx.x * blockDim.x + threadIdx.x;
-    if (ix >= P.nx) return;
-    const int iy = blockIdx.y, iz = blockIdx.z;
-    const int64_t x = (int64_t)ix + (int64_t)P.nx * ((int64_t)iy + (int64_t)P.ny * iz);
+    RowIdx r;
+    if (!row_index(P.nx, P.ny, r)) return;
+    const int64_t x = r.x;
     const int64_t S = P.S;
     if (flags[x] & FLAG_SOLID) {
         aux[x] = 0.0;
@@ -380,10 +564,10 @@ __global__ __launch_bounds__(256) void k_macro(const T* __restrict__ Nsrc, const
         return;
     }
     int64_t nb[Q];
-    neighbours<L>(ix, iy, iz, P.nx, P.ny, P.nz, nb);
+    neighbours<L>(r.ix, r.iy, r.iz, P.nx, P.ny, P.nz, nb);
     T N[Q], ph[Q];
 #pragma unroll
-    for (int i = 0; i < Q; i++) N[i] = Nsrc[(int64_t)i * S + x];
+    for (int i = 0; i < Q; i++) N[i] = NStore<T, SN>::dec(Nsrc[(int64_t)i * S + x], P.chi[i], P.n_s);
 #pragma unroll
     for (int i = 0; i < Q; i++) ph[i] = phi[nb[i]];
     Macro<T> m;
@@ -397,9 +581,10 @@ __global__ __launch_bounds__(256) void k_macro(const T* __restrict__ Nsrc, const
 
 // Diagnostics, stage 1: each block reduces a fixed strided set of nodes in a
 // fixed order (deterministic for a fixed grid).  Values: sum phi,
-// sum (1 - phi), sum rho u (3), max |u|, sum rho |u|^2 / 2.
-template <class L, class T>
-__global__ __launch_bounds__(256) void k_reduce1(const T* __restrict__ N, const T* __restrict__ B,
+// sum (1 - phi), sum rho u (3), max |u|, sum rho |u|^2 / 2; non-finite count
+// over N, the liquid state (B planes or compact record) and phi.
+template <class L, class T, class SN>
+__global__ __launch_bounds__(256) void k_reduce1(const SN* __restrict__ N, const T* __restrict__ Bstate, int nB,
                                                  const T* __restrict__ phi, const uint8_t* __restrict__ flags,
                                                  const double* __restrict__ aux, int64_t n, int64_t S, double rho_g,
                                                  double drho, double* __restrict__ partial,
@@ -424,10 +609,10 @@ __global__ __launch_bounds__(256) void k_reduce1(const T* __restrict__ N, const 
         v[5] = sp > v[5] ? sp : v[5];
         v[6] += 0.5 * rho * u2;
         if (!isfinite(ph) || !isfinite(u2)) bad++;
-        for (int i = 0; i < L::Q; i++) {
-            if (!isfinite((double)N[(int64_t)i * S + x])) bad++;
-            if (!isfinite((double)B[(int64_t)i * S + x])) bad++;
-        }
+        for (int i = 0; i < L::Q; i++)
+            if (!isfinite((double)(float)N[(int64_t)i * S + x])) bad++;
+        for (int i = 0; i < nB; i++)
+            if (!isfinite((double)Bstate[(int64_t)i * S + x])) bad++;
     }
     const int t = threadIdx.x;
     for (int k = 0; k < 7; k++) sh[k][t] = v[k];
@@ -486,20 +671,26 @@ __global__ __launch_bounds__(256) void k_reduce2(const double* __restrict__ part
 }
 
 // Start of a run: N = chi, B = phi chi at fluid nodes (u = p = 0), solid
-// phi = phi_solid in both colour buffers.
-template <class L, class T>
+// phi = phi_solid in both colour buffers, compact record zero.
+template <class L, class T, class SN>
 __global__ __launch_bounds__(256) void k_init(const double* __restrict__ phi0, const uint8_t* __restrict__ flags,
-                                              T* __restrict__ N, T* __restrict__ B, T* __restrict__ phiA,
-                                              T* __restrict__ phiB, KParams<T, L::Q> P, T phi_solid, int64_t n) {
+                                              SN* __restrict__ N, T* __restrict__ B, T* __restrict__ phiA,
+                                              T* __restrict__ phiB, T* __restrict__ G0, T* __restrict__ G1,
+                                              KParams<T, L::Q> P, T phi_solid, int64_t n) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     const int64_t S = P.S;
+#pragma unroll
+    for (int k = 0; k < GRec<L>::K; k++) {
+        G0[(int64_t)k * S + x] = T(0);
+        G1[(int64_t)k * S + x] = T(0);
+    }
     if (flags[x] & FLAG_SOLID) {
         phiA[x] = phi_solid;
         phiB[x] = phi_solid;
 #pragma unroll
         for (int i = 0; i < L::Q; i++) {
-            N[(int64_t)i * S + x] = T(0);
+            N[(int64_t)i * S + x] = NStore<T, SN>::enc(P.chi[i], P.chi[i], P.n_inv_s);
             B[(int64_t)i * S + x] = T(0);
         }
         return;
@@ -509,7 +700,7 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ phi0, c
     phiB[x] = ph;
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
-        N[(int64_t)i * S + x] = P.chi[i];
+        N[(int64_t)i * S + x] = NStore<T, SN>::enc(P.chi[i], P.chi[i], P.n_inv_s);
         B[(int64_t)i * S + x] = ph * P.chi[i];
     }
 }
@@ -533,11 +724,126 @@ __global__ __launch_bounds__(256) void k_plane_out(const T* __restrict__ src, co
     dst[x] = (zero_solid && (flags[x] & FLAG_SOLID)) ? 0.0 : (double)src[x];
 }
 
+// N plane `dir` <-> FP64 (decoding / encoding the storage).
+template <class T, class SN>
+__global__ __launch_bounds__(256) void k_nplane_out(const SN* __restrict__ src, const uint8_t* __restrict__ flags,
+                                                    T chi, T s, double* __restrict__ dst, int64_t n) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    dst[x] = (flags[x] & FLAG_SOLID) ? 0.0 : (double)NStore<T, SN>::dec(src[x], chi, s);
+}
+
+template <class T, class SN>
+__global__ __launch_bounds__(256) void k_nplane_in(const double* __restrict__ src, SN* __restrict__ dst, T chi,
+                                                   T inv_s, int64_t n) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    dst[x] = NStore<T, SN>::enc((T)src[x], chi, inv_s);
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_plane_in(const double* __restrict__ src, T* __restrict__ dst, int64_t n) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     dst[x] = (T)src[x];
+}
+
+// Solid entries of both colour buffers from an FP64 plane.
+template <class T>
+__global__ __launch_bounds__(256) void k_solid_in(const double* __restrict__ src, const uint8_t* __restrict__ flags,
+                                                  T* __restrict__ phiA, T* __restrict__ phiB, int64_t n) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    if (flags[x] & FLAG_SOLID) {
+        phiA[x] = (T)src[x];
+        phiB[x] = (T)src[x];
+    }
+}
+
+// ------------------------------------------------------------------ batched steps
+// Many independent runs advance in shared launches: every workgroup (one
+// wave, 64 threads) finds its job by binary search over the jobs' first
+// block, then works on one row-block of that job exactly as the single-run
+// kernels do.  Jobs are sorted by their sub-step count (largest first), so
+// the jobs still active at sub-step k are a prefix and the grid shrinks.
+constexpr int BATCH_BX = 64;
+
+template <class L, class T, class SN>
+struct BJob {
+    KParams<T, L::Q> P;
+    const SN* N[2];
+    T* G[2];
+    T* phi[2];
+    const T* B;
+    const uint8_t* flags;
+    const int32_t* g_node;
+    const int32_t* g_corner;
+    const T* g_w;
+    const uint8_t* g_mask;
+    int32_t n_ghost;
+    int32_t rule;
+    T E, eps;
+    int32_t cur0, ps0, planes0, nxb;
+};
+
+__device__ __forceinline__ int find_job(const int64_t* __restrict__ start, int njobs, int64_t b) {
+    int lo = 0, hi = njobs - 1;   // largest j with start[j] <= b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (start[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <class L, class T, class SN>
+__device__ __forceinline__ bool batch_row(const BJob<L, T, SN>& J, int64_t lb, int& ix, int& iy, int& iz) {
+    const int64_t row = lb / J.nxb;
+    ix = (int)(lb - row * J.nxb) * BATCH_BX + (int)threadIdx.x;
+    iy = (int)(row % J.P.ny);
+    iz = (int)(row / J.P.ny);
+    return ix < J.P.nx;
+}
+
+template <class L, class T, class SN>
+__global__ __launch_bounds__(BATCH_BX) void kb_colour(const BJob<L, T, SN>* __restrict__ jobs,
+                                                      const int64_t* __restrict__ start, int njobs, int64_t k) {
+    const int j = find_job(start, njobs, blockIdx.x);
+    const BJob<L, T, SN>& J = jobs[j];
+    int ix, iy, iz;
+    if (!batch_row(J, (int64_t)blockIdx.x - start[j], ix, iy, iz)) return;
+    const int par = (int)((J.cur0 + k) & 1), pps = (int)((J.ps0 + k) & 1);
+    T* work = J.phi[1 - pps];
+    if (k == 0 && J.planes0) {
+        const int64_t x = (int64_t)ix + (int64_t)J.P.nx * ((int64_t)iy + (int64_t)J.P.ny * iz);
+        colour_planes_node<L, T>(J.B, work, J.flags, x, J.P.S);
+    } else {
+        colour_compact_node<L, T, SN>(J.N[par], J.phi[pps], J.G[par], J.flags, work, J.P, ix, iy, iz);
+    }
+}
+
+template <class L, class T, class SN>
+__global__ __launch_bounds__(BATCH_BX) void kb_ghost(const BJob<L, T, SN>* __restrict__ jobs,
+                                                     const int64_t* __restrict__ start, int njobs, int64_t k) {
+    const int j = find_job(start, njobs, blockIdx.x);
+    const BJob<L, T, SN>& J = jobs[j];
+    const int g = (int)((int64_t)blockIdx.x - start[j]) * BATCH_BX + (int)threadIdx.x;
+    if (g >= J.n_ghost) return;
+    const int pps = (int)((J.ps0 + k) & 1);
+    ghost_one<T, L::NC>(J.g_node, J.g_corner, J.g_w, J.g_mask, J.n_ghost, J.phi[pps], J.phi[1 - pps], J.E, J.eps,
+                        J.rule, g);
+}
+
+template <class L, class T, class SN>
+__global__ __launch_bounds__(BATCH_BX) void kb_collide(const BJob<L, T, SN>* __restrict__ jobs,
+                                                       const int64_t* __restrict__ start, int njobs, int64_t k) {
+    const int j = find_job(start, njobs, blockIdx.x);
+    const BJob<L, T, SN>& J = jobs[j];
+    int ix, iy, iz;
+    if (!batch_row(J, (int64_t)blockIdx.x - start[j], ix, iy, iz)) return;
+    const int par = (int)((J.cur0 + k) & 1), pps = (int)((J.ps0 + k) & 1);
+    collide_node<L, T, SN>(J.N[par], const_cast<SN*>(J.N[1 - par]), J.G[1 - par], J.phi[1 - pps], J.flags, J.P, ix,
+                           iy, iz);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -547,14 +853,25 @@ static inline dim3 row_grid(const StepParams& p, int bx) {
     return dim3((unsigned)((p.nx + bx - 1) / bx), (unsigned)p.ny, (unsigned)p.nz);
 }
 
-static inline int row_block(int nx) { return nx >= 256 ? 256 : (nx >= 128 ? 128 : 64); }
+static inline int row_block(int nx) {
+    int b = nx >= 256 ? 256 : (nx >= 128 ? 128 : 64);
+    return b > LBM_COLLIDE_BX ? LBM_COLLIDE_BX : b;
+}
 
-template <class L, class T>
-static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int cur, int ps, hipStream_t st) {
+template <class L, class T, class SN>
+static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int cur, int ps, int from_planes,
+                          hipStream_t st) {
     T* work = (T*)d.phi[1 - ps];
+    const int bx = row_block(p.nx);
     if (phase == 0) {
-        hipLaunchKernelGGL((k_colour<L, T>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st, (const T*)d.B[cur], work,
-                           d.flags, p.n, p.S);
+        if (from_planes) {
+            hipLaunchKernelGGL((k_colour_planes<L, T>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st,
+                               (const T*)d.B, work, d.flags, p.n, p.S);
+        } else {
+            const KParams<T, L::Q> kp = make_kparams<T, L, SN>(p);
+            hipLaunchKernelGGL((k_colour_compact<L, T, SN>), row_grid(p, bx), dim3(bx), 0, st, (const SN*)d.N[cur],
+                               (const T*)d.phi[ps], (const T*)d.G[cur], d.flags, work, kp);
+        }
     } else if (phase == 1) {
         if (d.n_ghost > 0) {
             hipLaunchKernelGGL((k_ghost<T, L::NC>), dim3(blocks_for(d.n_ghost, 256)), dim3(256), 0, st, d.g_node,
@@ -562,128 +879,231 @@ static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int
                                (T)p.exp_eps, (T)p.eps, p.ghost_rule);
         }
     } else {
-        const KParams<T, L::Q> kp = make_kparams<T, L>(p);
-        const int bx = row_block(p.nx);
-        hipLaunchKernelGGL((k_collide_stream<L, T>), row_grid(p, bx), dim3(bx), 0, st, (const T*)d.N[cur],
-                           (T*)d.N[1 - cur], (T*)d.B[1 - cur], (const T*)work, d.flags, kp);
+        const KParams<T, L::Q> kp = make_kparams<T, L, SN>(p);
+        hipLaunchKernelGGL((k_collide_stream<L, T, SN>), row_grid(p, bx), dim3(bx), 0, st, (const SN*)d.N[cur],
+                           (SN*)d.N[1 - cur], (T*)d.G[1 - cur], (const T*)work, d.flags, kp);
     }
     return hipGetLastError();
 }
 
-template <class L, class T>
-static hipError_t colour_t(const DevState& d, const StepParams& p, int cur, int ps, hipStream_t st) {
-    hipError_t e = phase_t<L, T>(0, d, p, cur, ps, st);
+template <class L, class T, class SN>
+static hipError_t colour_t(const DevState& d, const StepParams& p, int cur, int ps, int from_planes,
+                           hipStream_t st) {
+    hipError_t e = phase_t<L, T, SN>(0, d, p, cur, ps, from_planes, st);
     if (e != hipSuccess) return e;
-    return phase_t<L, T>(1, d, p, cur, ps, st);
+    return phase_t<L, T, SN>(1, d, p, cur, ps, from_planes, st);
 }
 
-template <class L, class T>
-static hipError_t step_t(const DevState& d, const StepParams& p, int cur, int ps, hipStream_t st) {
+template <class L, class T, class SN>
+static hipError_t step_t(const DevState& d, const StepParams& p, int cur, int ps, int from_planes, hipStream_t st) {
     for (int ph = 0; ph < 3; ph++) {
-        hipError_t e = phase_t<L, T>(ph, d, p, cur, ps, st);
+        hipError_t e = phase_t<L, T, SN>(ph, d, p, cur, ps, from_planes, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-template <class L, class T>
+template <class L, class T, class SN>
 static hipError_t macro_t(const DevState& d, const StepParams& p, int cur, int ps, hipStream_t st) {
-    const KParams<T, L::Q> kp = make_kparams<T, L>(p);
+    const KParams<T, L::Q> kp = make_kparams<T, L, SN>(p);
     const int bx = row_block(p.nx);
-    hipLaunchKernelGGL((k_macro<L, T>), row_grid(p, bx), dim3(bx), 0, st, (const T*)d.N[cur],
+    hipLaunchKernelGGL((k_macro<L, T, SN>), row_grid(p, bx), dim3(bx), 0, st, (const SN*)d.N[cur],
                        (const T*)d.phi[1 - ps], d.flags, kp, d.aux);
     return hipGetLastError();
 }
 
-template <class L, class T>
-static hipError_t reduce_t(const DevState& d, const StepParams& p, int cur, int ps, hipStream_t st) {
-    hipLaunchKernelGGL((k_reduce1<L, T>), dim3(REDUCE_BLOCKS), dim3(256), 0, st, (const T*)d.N[cur],
-                       (const T*)d.B[cur], (const T*)d.phi[1 - ps], d.flags, d.aux, p.n, p.S, p.rho_g,
-                       p.rho_l - p.rho_g, d.partial, d.nonfinite);
+template <class L, class T, class SN>
+static hipError_t reduce_t(const DevState& d, const StepParams& p, int cur, int ps, int from_planes,
+                           hipStream_t st) {
+    const T* Bstate = from_planes ? (const T*)d.B : (const T*)d.G[cur];
+    const int nB = from_planes ? L::Q : GRec<L>::K;
+    hipLaunchKernelGGL((k_reduce1<L, T, SN>), dim3(REDUCE_BLOCKS), dim3(256), 0, st, (const SN*)d.N[cur], Bstate, nB,
+                       (const T*)d.phi[1 - ps], d.flags, d.aux, p.n, p.S, p.rho_g, p.rho_l - p.rho_g, d.partial,
+                       d.nonfinite);
     hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(256), 0, st, d.partial, d.nonfinite, REDUCE_BLOCKS, d.result,
                        d.nonfinite + REDUCE_BLOCKS);
     return hipGetLastError();
 }
 
-template <class L, class T>
+template <class L, class T, class SN>
 static hipError_t init_t(const DevState& d, const StepParams& p, int cur, int ps, hipStream_t st) {
-    const KParams<T, L::Q> kp = make_kparams<T, L>(p);
-    hipLaunchKernelGGL((k_init<L, T>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st, d.aux, d.flags, (T*)d.N[cur],
-                       (T*)d.B[cur], (T*)d.phi[0], (T*)d.phi[1], kp, (T)p.phi_solid, p.n);
+    const KParams<T, L::Q> kp = make_kparams<T, L, SN>(p);
+    hipLaunchKernelGGL((k_init<L, T, SN>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st, d.aux, d.flags, (SN*)d.N[cur],
+                       (T*)d.B, (T*)d.phi[0], (T*)d.phi[1], (T*)d.G[0], (T*)d.G[1], kp, (T)p.phi_solid, p.n);
     (void)ps;
     return hipGetLastError();
 }
 
-template <class L, class T>
-static hipError_t plane_out_t(const DevState& d, const StepParams& p, int which, int dir, int cur, hipStream_t st) {
-    const T* src = which == 0 ? (const T*)d.N[cur] + (int64_t)dir * p.S
-                 : which == 1 ? (const T*)d.B[cur] + (int64_t)dir * p.S
-                              : (const T*)d.phi[dir];
+// which: 0 = N plane `dir` of buffer cur, 1 = B plane `dir` (planes buffer
+// when from_planes, else formed from the compact record), 2 = phi buffer `dir`.
+template <class L, class T, class SN>
+static hipError_t plane_out_t(const DevState& d, const StepParams& p, int which, int dir, int cur, int ps,
+                              int from_planes, hipStream_t st) {
+    if (which == 1 && !from_planes) {
+        const KParams<T, L::Q> kp = make_kparams<T, L, SN>(p);
+        const int bx = row_block(p.nx);
+        hipLaunchKernelGGL((k_compact_B_plane<L, T, SN>), row_grid(p, bx), dim3(bx), 0, st, (const SN*)d.N[cur],
+                           (const T*)d.phi[ps], (const T*)d.G[cur], d.flags, kp, dir, d.aux);
+        return hipGetLastError();
+    }
+    if (which == 0) {
+        hipLaunchKernelGGL((k_nplane_out<T, SN>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st,
+                           (const SN*)d.N[cur] + (int64_t)dir * p.S, d.flags, (T)p.chi[dir],
+                           (T)(NStore<T, SN>::offset ? N16_SCALE : 1.0), d.aux, p.n);
+        return hipGetLastError();
+    }
+    const T* src = which == 1 ? (const T*)d.B + (int64_t)dir * p.S : (const T*)d.phi[dir];
     hipLaunchKernelGGL((k_plane_out<T>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st, src, d.flags,
                        which < 2 ? 1 : 0, d.aux, p.n);
     return hipGetLastError();
 }
 
-template <class L, class T>
+// which: 0 = N plane `dir` of buffer cur, 1 = B plane `dir` (planes buffer),
+// 2 = solid entries of both phi buffers.
+template <class L, class T, class SN>
 static hipError_t plane_in_t(const DevState& d, const StepParams& p, int which, int dir, int cur, hipStream_t st) {
-    T* dst = which == 0 ? (T*)d.N[cur] + (int64_t)dir * p.S
-           : which == 1 ? (T*)d.B[cur] + (int64_t)dir * p.S
-                        : (T*)d.phi[dir];
+    if (which == 2) {
+        hipLaunchKernelGGL((k_solid_in<T>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st, d.aux, d.flags,
+                           (T*)d.phi[0], (T*)d.phi[1], p.n);
+        return hipGetLastError();
+    }
+    if (which == 0) {
+        hipLaunchKernelGGL((k_nplane_in<T, SN>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st, d.aux,
+                           (SN*)d.N[cur] + (int64_t)dir * p.S, (T)p.chi[dir],
+                           (T)(NStore<T, SN>::offset ? 1.0 / N16_SCALE : 1.0), p.n);
+        return hipGetLastError();
+    }
+    T* dst = (T*)d.B + (int64_t)dir * p.S;
     hipLaunchKernelGGL((k_plane_in<T>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st, d.aux, dst, p.n);
     return hipGetLastError();
 }
 
 // Dispatch on lattice and arithmetic type.
+#define LBM_DISPATCH_L(FN, T, SN, ...)                                                \
+    do {                                                                              \
+        if (lattice == 0) return FN<LatD2Q9, T, SN>(__VA_ARGS__);                     \
+        return FN<LatD3Q19, T, SN>(__VA_ARGS__);                                      \
+    } while (0)
 #define LBM_DISPATCH(FN, ...)                                                         \
     do {                                                                              \
-        if (prec == P_FP64) {                                                         \
-            if (lattice == 0) return FN<LatD2Q9, double>(__VA_ARGS__);                \
-            return FN<LatD3Q19, double>(__VA_ARGS__);                                 \
+        switch (prec) {                                                               \
+        case P_FP64: LBM_DISPATCH_L(FN, double, double, __VA_ARGS__);                 \
+        case P_FP32: LBM_DISPATCH_L(FN, float, float, __VA_ARGS__);                   \
+        case P_FP16_OFS: LBM_DISPATCH_L(FN, float, _Float16, __VA_ARGS__);            \
+        case P_BF16_OFS: LBM_DISPATCH_L(FN, float, __bf16, __VA_ARGS__);              \
+        default: return hipErrorNotSupported;                                         \
         }                                                                             \
-        if (prec == P_FP32) {                                                         \
-            if (lattice == 0) return FN<LatD2Q9, float>(__VA_ARGS__);                 \
-            return FN<LatD3Q19, float>(__VA_ARGS__);                                  \
-        }                                                                             \
-        return hipErrorNotSupported;                                                  \
     } while (0)
 
 hipError_t launch_step(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
-                       hipStream_t st) {
-    LBM_DISPATCH(step_t, d, p, cur, ps, st);
+                       int from_planes, hipStream_t st) {
+    LBM_DISPATCH(step_t, d, p, cur, ps, from_planes, st);
 }
 hipError_t launch_phase(int lattice, uint32_t prec, int phase, const DevState& d, const StepParams& p, int cur,
-                        int ps, hipStream_t st) {
-    LBM_DISPATCH(phase_t, phase, d, p, cur, ps, st);
+                        int ps, int from_planes, hipStream_t st) {
+    LBM_DISPATCH(phase_t, phase, d, p, cur, ps, from_planes, st);
 }
 hipError_t launch_colour(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
-                         hipStream_t st) {
-    LBM_DISPATCH(colour_t, d, p, cur, ps, st);
+                         int from_planes, hipStream_t st) {
+    LBM_DISPATCH(colour_t, d, p, cur, ps, from_planes, st);
 }
 hipError_t launch_macro(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
                         hipStream_t st) {
     LBM_DISPATCH(macro_t, d, p, cur, ps, st);
 }
 hipError_t launch_reduce(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
-                         hipStream_t st) {
-    LBM_DISPATCH(reduce_t, d, p, cur, ps, st);
+                         int from_planes, hipStream_t st) {
+    LBM_DISPATCH(reduce_t, d, p, cur, ps, from_planes, st);
 }
 hipError_t launch_init(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
                        hipStream_t st) {
     LBM_DISPATCH(init_t, d, p, cur, ps, st);
 }
 hipError_t launch_plane_out(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int which, int dir,
-                            int cur, hipStream_t st) {
-    LBM_DISPATCH(plane_out_t, d, p, which, dir, cur, st);
+                            int cur, int ps, int from_planes, hipStream_t st) {
+    LBM_DISPATCH(plane_out_t, d, p, which, dir, cur, ps, from_planes, st);
 }
 hipError_t launch_plane_in(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int which, int dir,
                            int cur, hipStream_t st) {
     LBM_DISPATCH(plane_in_t, d, p, which, dir, cur, st);
 }
+size_t batch_table_bytes(int max_jobs) {
+    size_t per = sizeof(BJob<LatD3Q19, double, double>) + 2 * sizeof(int64_t);
+    return (size_t)max_jobs * per + 16 * 256;
+}
+
+template <class L, class T, class SN>
+static hipError_t batch_t(const BatchJobHost* jobs, int nj, void* table, size_t table_bytes, int64_t nsteps,
+                          hipStream_t st, std::vector<char>& staging) {
+    using J = BJob<L, T, SN>;
+    const size_t jb = ((sizeof(J) * (size_t)nj) + 255) & ~size_t(255);
+    const size_t sb = (((size_t)nj + 1) * sizeof(int64_t) + 255) & ~size_t(255);
+    const size_t need = jb + 2 * sb;
+    if (need > table_bytes) return hipErrorInvalidValue;
+    staging.assign(need, 0);
+    J* dj = reinterpret_cast<J*>(staging.data());
+    int64_t* rs = reinterpret_cast<int64_t*>(staging.data() + jb);
+    int64_t* gs = reinterpret_cast<int64_t*>(staging.data() + jb + sb);
+    rs[0] = gs[0] = 0;
+    for (int j = 0; j < nj; j++) {
+        const BatchJobHost& h = jobs[j];
+        J& o = dj[j];
+        o.P = make_kparams<T, L, SN>(h.p);
+        for (int b = 0; b < 2; b++) {
+            o.N[b] = (const SN*)h.d.N[b];
+            o.G[b] = (T*)h.d.G[b];
+            o.phi[b] = (T*)h.d.phi[b];
+        }
+        o.B = (const T*)h.d.B;
+        o.flags = h.d.flags;
+        o.g_node = h.d.g_node;
+        o.g_corner = h.d.g_corner;
+        o.g_w = (const T*)h.d.g_w;
+        o.g_mask = h.d.g_mask;
+        o.n_ghost = h.d.n_ghost;
+        o.rule = h.p.ghost_rule;
+        o.E = (T)h.p.exp_eps;
+        o.eps = (T)h.p.eps;
+        o.cur0 = h.cur0;
+        o.ps0 = h.ps0;
+        o.planes0 = h.planes0;
+        o.nxb = (h.p.nx + BATCH_BX - 1) / BATCH_BX;
+        rs[j + 1] = rs[j] + (int64_t)o.nxb * h.p.ny * h.p.nz;
+        gs[j + 1] = gs[j] + (h.d.n_ghost + BATCH_BX - 1) / BATCH_BX;
+    }
+    char* tb = (char*)table;
+    hipError_t e = hipMemcpyAsync(tb, staging.data(), need, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    const J* djd = (const J*)tb;
+    const int64_t* rsd = (const int64_t*)(tb + jb);
+    const int64_t* gsd = (const int64_t*)(tb + jb + sb);
+    int active = nj;
+    for (int64_t k = 0; k < nsteps; k++) {
+        while (active > 0 && jobs[active - 1].steps <= k) active--;
+        if (active == 0) break;
+        hipLaunchKernelGGL((kb_colour<L, T, SN>), dim3((unsigned)rs[active]), dim3(BATCH_BX), 0, st, djd, rsd, active,
+                           k);
+        if (gs[active] > 0)
+            hipLaunchKernelGGL((kb_ghost<L, T, SN>), dim3((unsigned)gs[active]), dim3(BATCH_BX), 0, st, djd, gsd,
+                               active, k);
+        hipLaunchKernelGGL((kb_collide<L, T, SN>), dim3((unsigned)rs[active]), dim3(BATCH_BX), 0, st, djd, rsd,
+                           active, k);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_batch(int lattice, uint32_t prec, const BatchJobHost* jobs, int njobs, void* table,
+                        size_t table_bytes, int64_t nsteps, hipStream_t st, std::vector<char>& staging) {
+    LBM_DISPATCH(batch_t, jobs, njobs, table, table_bytes, nsteps, st, staging);
+}
+
 hipError_t launch_solid_phi(uint32_t prec, const DevState& d, const StepParams& p, hipStream_t st) {
     if (prec == P_FP64) {
         hipLaunchKernelGGL((k_solid_phi<double>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st, d.flags,
                            (double*)d.phi[0], (double*)d.phi[1], p.phi_solid, p.n);
-    } else if (prec == P_FP32) {
+    } else if (prec == P_FP32 || prec == P_FP16_OFS || prec == P_BF16_OFS) {
         hipLaunchKernelGGL((k_solid_phi<float>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st, d.flags,
                            (float*)d.phi[0], (float*)d.phi[1], (float)p.phi_solid, p.n);
     } else {

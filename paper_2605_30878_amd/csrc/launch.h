@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace lbm {
 
@@ -29,8 +30,10 @@ struct StepParams {
 // Device memory of one run, carved from the caller's buffer.
 struct DevState {
     void* N[2];         // [Q][S] colour-blind populations, ping-pong
-    void* B[2];         // [Q][S] liquid populations, ping-pong
-    void* phi[2];       // [S] colour field; phi[state] holds the solid values
+    void* B;            // [Q][S] liquid populations of the initial state or a restore
+    void* G[2];         // [D+1][S] compact liquid record (G components, p), ping-pong with N
+    void* phi[2];       // [S] colour field; phi[state] holds the solid values and
+                        //     the previous step's phi at fluid nodes
     uint8_t* flags;     // [S] node classes
     int32_t* g_node;    // [n_ghost]
     int32_t* g_corner;  // [NC][n_ghost] interpolation corners of x_F
@@ -48,34 +51,56 @@ constexpr int REDUCE_BLOCKS = 1024;
 enum Precision : uint32_t { P_FP64 = 0, P_FP32 = 1, P_FP16_OFS = 2, P_BF16_OFS = 3 };
 
 // All launchers enqueue on `stream` and return hipGetLastError().
-// `cur` is the population buffer holding the state, `ps` the phi buffer
-// holding the solid values of the state.
+// `cur` is the population / compact-record buffer holding the state, `ps`
+// the phi buffer holding the state's solid values (and the previous step's
+// phi at fluid nodes).  `from_planes` != 0: the liquid state is the B plane
+// buffer (initial state or restore) instead of the compact record.
 hipError_t launch_step(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
-                       hipStream_t stream);
+                       int from_planes, hipStream_t stream);
 // One phase of a step: 0 = colour field, 1 = ghost update, 2 = fused
 // collide-stream (the three launches of launch_step, in that order).
 hipError_t launch_phase(int lattice, uint32_t prec, int phase, const DevState& d, const StepParams& p, int cur,
-                        int ps, hipStream_t stream);
+                        int ps, int from_planes, hipStream_t stream);
 // Colour field and ghost update into phi[1 - ps] (the phi the next step uses).
 hipError_t launch_colour(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
-                         hipStream_t stream);
+                         int from_planes, hipStream_t stream);
 // u and p of every fluid node into aux (after launch_colour).
 hipError_t launch_macro(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
                         hipStream_t stream);
 // Diagnostics into d.result / d.nonfinite (after launch_macro).
 hipError_t launch_reduce(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
-                         hipStream_t stream);
+                         int from_planes, hipStream_t stream);
 // Start of a run from the FP64 phi in aux[0]: N = chi, B = phi chi at fluid
 // nodes, phi of solid nodes (both buffers) = phi_solid.
 hipError_t launch_init(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
                        hipStream_t stream);
 // Solid nodes of both phi buffers = phi_solid.
 hipError_t launch_solid_phi(uint32_t prec, const DevState& d, const StepParams& p, hipStream_t stream);
-// Convert one plane between storage and FP64 aux[0].  which: 0 = N, 1 = B,
-// 2 = phi buffer `dir`; for N/B, `dir` is the direction, buffer `cur`.
+// One plane to FP64 aux[0].  which: 0 = N plane `dir`, 1 = B plane `dir`
+// (formed from the compact record unless from_planes), 2 = phi buffer `dir`.
 hipError_t launch_plane_out(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int which,
-                            int dir, int cur, hipStream_t stream);
+                            int dir, int cur, int ps, int from_planes, hipStream_t stream);
+// One plane from FP64 aux[0].  which: 0 = N plane `dir`, 1 = B plane `dir`
+// of the plane buffer, 2 = solid entries of both phi buffers.
 hipError_t launch_plane_in(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int which,
                            int dir, int cur, hipStream_t stream);
+
+// One job of a batched step: a started context's device state, constants,
+// state buffers at the first sub-step, and how many sub-steps it takes.
+struct BatchJobHost {
+    DevState d;
+    StepParams p;
+    int32_t cur0, ps0, planes0;
+    int64_t steps;
+};
+
+// Device bytes of a batch job table for up to max_jobs jobs (all groups).
+size_t batch_table_bytes(int max_jobs);
+// Advance every job of one (lattice, precision) group by its `steps`
+// (<= nsteps) with one launch per phase and sub-step for the whole group.
+// Jobs must be sorted by steps, largest first.  The table is uploaded from
+// `staging` (kept alive by the caller until the stream has passed it).
+hipError_t launch_batch(int lattice, uint32_t prec, const BatchJobHost* jobs, int njobs, void* table,
+                        size_t table_bytes, int64_t nsteps, hipStream_t stream, std::vector<char>& staging);
 
 }  // namespace lbm

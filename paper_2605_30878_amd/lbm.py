@@ -24,7 +24,8 @@ FLAG_SOLID, FLAG_NEAR_SOLID, FLAG_GHOST = 1, 2, 4
 
 EXPORTED = ["lbm_create", "lbm_set_geometry", "lbm_device_bytes", "lbm_bind", "lbm_set_wetting",
             "lbm_set_field", "lbm_step", "lbm_step_profiled", "lbm_observe", "lbm_read_field",
-            "lbm_lattice", "lbm_destroy", "lbm_last_error"]
+            "lbm_lattice", "lbm_destroy", "lbm_last_error", "lbm_batch_table_bytes", "lbm_batch_create",
+            "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_last_error"]
 
 
 class LbmError(RuntimeError):
@@ -79,8 +80,14 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_destroy.argtypes = [vp]
     lib.lbm_last_error.argtypes = [vp]
     lib.lbm_last_error.restype = C.c_char_p
+    lib.lbm_batch_table_bytes.argtypes = [C.c_int32, C.POINTER(C.c_size_t)]
+    lib.lbm_batch_create.argtypes = [vp, C.c_size_t, vp, C.POINTER(vp)]
+    lib.lbm_batch_step.argtypes = [vp, C.POINTER(vp), C.POINTER(C.c_int64), C.c_int32]
+    lib.lbm_batch_destroy.argtypes = [vp]
+    lib.lbm_batch_last_error.argtypes = [vp]
+    lib.lbm_batch_last_error.restype = C.c_char_p
     for name in EXPORTED:
-        if name != "lbm_last_error":
+        if name not in ("lbm_last_error", "lbm_batch_last_error"):
             getattr(lib, name).restype = C.c_int
     _lib = lib
     return lib
@@ -211,3 +218,47 @@ class Simulation:
                 "nonfinite": o.nonfinite, "mass_blue": o.mass_blue, "mass_red": o.mass_red,
                 "momentum": [o.momentum[0], o.momentum[1], o.momentum[2]], "max_speed": o.max_speed,
                 "kinetic_energy": o.kinetic_energy, "rc": rc}
+
+
+class Batch:
+    """Shared-launch stepping of many Simulations (lbm_batch_*).  The job
+    table is a torch device buffer; launches go to `stream` (default: the
+    current stream), which every member Simulation must also use."""
+
+    def __init__(self, max_jobs: int = 512, device: str = "cuda:0", stream=None):
+        import torch
+
+        lib = load_library()
+        self.lib = lib
+        nbytes = C.c_size_t()
+        rc = lib.lbm_batch_table_bytes(int(max_jobs), C.byref(nbytes))
+        if rc != OK:
+            raise LbmError(rc, "bad max_jobs")
+        self.table = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=torch.device(device))
+        aligned = (self.table.data_ptr() + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
+        h = C.c_void_p()
+        rc = lib.lbm_batch_create(C.c_void_p(aligned), nbytes.value, C.c_void_p(self.stream.cuda_stream), C.byref(h))
+        if rc != OK:
+            raise LbmError(rc, lib.lbm_batch_last_error(None).decode())
+        self._h = h
+
+    def step(self, sims: Sequence["Simulation"], steps: Sequence[int]):
+        n = len(sims)
+        arr = (C.c_void_p * max(n, 1))(*[s._h for s in sims])
+        st = (C.c_int64 * max(n, 1))(*[int(k) for k in steps])
+        rc = self.lib.lbm_batch_step(self._h, arr, st, n)
+        if rc != OK:
+            raise LbmError(rc, self.lib.lbm_batch_last_error(self._h).decode())
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            self.lib.lbm_batch_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,71 @@
+"""Write tests/golden/sphere64_oracle.json: the FP64 oracle's equilibrium
+measurements of the D3Q19 drop on a sphere in a 64^3 box (sphere radius 12
+at the centre, drop radius 10 on its top, density ratio 1000, viscosity
+ratio 100, W = 4, sigma = 0.01) after 20000 steps, for each contact angle.
+
+Only the oracle computes the fields; the FP64 numpy post-processing in
+paper_2605_30878_amd/measure.py (the same fit the GPU test applies to the
+library's output) turns them into angles and heights.  Run:
+    OMP_NUM_THREADS=8 python tests/golden/make_sphere64.py [theta ...]
+(about 20 minutes per angle on 8 cores)."""
+import json
+import math
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+from paper_2605_30878_amd import measure  # noqa: E402
+from paper_2605_30878_amd import workloads as W  # noqa: E402
+
+OUT = os.path.join(HERE, "sphere64_oracle.json")
+STEPS = 20000
+
+
+def measure_state(sim, wl):
+    n = wl.shape[0]
+    solid = sim.get(oracle.F_SOLID) > 0.5
+    phi = sim.get(oracle.F_PHI)
+    u = sim.get(oracle.F_U)
+    p = sim.get(oracle.F_P)
+    rho = sim.get(oracle.F_RHO)
+    c = n / 2.0
+    R = wl.solids[0].radius
+    fit = measure.curved_contact_angle(phi, wl.shape, solid, (c, c, c), R, wl.W, dim=3)
+    apex = measure.apex_height(phi, wl.shape, (n // 2, n // 2, 0), c + R, axis=2) - c
+    ph = rho * p
+    fluid = ~solid
+    speed = np.sqrt((u * u).sum(axis=0))
+    return {"theta_fit": fit["theta"], "Rc": fit["Rc"], "d": fit["d"], "apex": apex,
+            "dp_h": float(ph[fluid & (phi > 0.999)].mean() - ph[fluid & (phi < 0.001)].mean()),
+            "max_speed": float(speed[fluid].max()), "mass_blue": float(phi[fluid].sum())}
+
+
+def main(thetas):
+    data = {}
+    if os.path.exists(OUT):
+        data = json.load(open(OUT))
+    for th in thetas:
+        wl = W.sphere_d3q19(64, theta=th, precision=W.FP64, steps=STEPS)
+        sim = oracle.OracleSim(wl, W.initial_phi(wl))
+        t0 = time.time()
+        rec = {"steps": STEPS, "checkpoints": {}}
+        for k in range(1, 5):
+            sim.step(STEPS // 4)
+            rec["checkpoints"][str(k * STEPS // 4)] = measure_state(sim, wl)
+            print(th, k * STEPS // 4, rec["checkpoints"][str(k * STEPS // 4)], f"{time.time() - t0:.0f}s",
+                  flush=True)
+        rec.update(rec["checkpoints"][str(STEPS)])
+        data[str(float(th))] = rec
+        with open(OUT, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main([float(a) for a in sys.argv[1:]] or [30.0, 60.0, 90.0, 120.0, 150.0])

@@ -80,14 +80,15 @@ def test_call_order_is_enforced():
 
 
 def test_device_bytes_cover_the_state():
-    """Two population buffers of N and B (Q planes each) plus the rest."""
+    """Two buffers of N (Q planes each), the B plane buffer and two compact
+    liquid records (D + 1 planes each), plus the rest."""
     lib = lbm.load_library()
     wl = W.sphere_d3q19(64, precision=W.FP32)
     rc, h = _create(wl)
     assert lib.lbm_set_geometry(h, lbm.make_solids(wl.solids), 1) == lbm.OK
     nbytes = C.c_size_t()
     lib.lbm_device_bytes(h, C.byref(nbytes))
-    assert nbytes.value >= 4 * 19 * 64 ** 3 * 4
+    assert nbytes.value >= (3 * 19 + 2 * 4) * 64 ** 3 * 4
     lib.lbm_destroy(h)
 
 

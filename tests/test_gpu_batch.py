@@ -1,0 +1,103 @@
+"""Continuous batching on the GPU: runs advanced together with shared
+launches (lbm_batch_step) compute exactly what each computes alone
+(lbm_step), while runs join and leave between calls; a small served mix
+finishes every request and matches single runs."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2605_30878_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _lbm():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2605_30878_amd import lbm
+
+    lbm.load_library()
+    return lbm
+
+
+def _jobs():
+    return [
+        W.cylinder_d2q9_128(theta=30.0),
+        W.cylinder_d2q9_128(theta=150.0, precision=W.FP32),
+        W.sphere_d3q19(32, theta=60.0, precision=W.FP32),
+        W.sphere_d3q19(24, theta=120.0, precision=W.FP16_OFS),
+        W.sphere_d3q19(24, theta=45.0, precision=W.BF16_OFS),
+        W.free_drop(W.D2Q9, 40, 9.0, rho_ratio=3.0),
+        W.plate_d2q9(70, 36, 120.0, 12.0, rho_ratio=10.0, mu_ratio=10.0),
+    ]
+
+
+def _state(lbm, sim):
+    return sim.read(lbm.FIELD_N), sim.read(lbm.FIELD_B), sim.read(lbm.FIELD_PHI)
+
+
+def test_batch_equals_single_runs_with_joins_and_leaves():
+    lbm = _lbm()
+    jobs = _jobs()
+    # per-call step counts: runs join late (0 first) and leave early (0 last)
+    plan = np.array([[5, 0, 7, 3, 9, 2, 4],
+                     [11, 6, 0, 8, 1, 5, 0],
+                     [0, 9, 4, 2, 6, 0, 7]])
+    total = plan.sum(axis=0)
+    print(f"[batch] jobs={len(jobs)} total steps={total.tolist()}", flush=True)
+    alone = []
+    for wl, n in zip(jobs, total):
+        s = lbm.Simulation(wl, W.initial_phi(wl))
+        s.step(int(n))
+        alone.append(_state(lbm, s))
+        s.close()
+    sims = [lbm.Simulation(wl, W.initial_phi(wl)) for wl in jobs]
+    batch = lbm.Batch(max_jobs=16)
+    for row in plan:
+        active = [k for k in range(len(jobs)) if row[k] > 0]
+        batch.step([sims[k] for k in active], [int(row[k]) for k in active])
+    for k, sim in enumerate(sims):
+        got = _state(lbm, sim)
+        for a, b, name in zip(got, alone[k], ("N", "B", "phi")):
+            assert np.array_equal(a, b), (jobs[k].name, name, float(np.max(np.abs(a - b))))
+        assert sim.observe()["step"] == total[k]
+        sim.close()
+    batch.close()
+
+
+def test_batch_rejects_bad_calls():
+    lbm = _lbm()
+    wl = W.cylinder_d2q9_128()
+    sim = lbm.Simulation(wl, W.initial_phi(wl))
+    batch = lbm.Batch(max_jobs=2)
+    with pytest.raises(lbm.LbmError):
+        batch.step([sim, sim], [1, 1])
+    with pytest.raises(lbm.LbmError):
+        batch.step([sim], [-1])
+    batch.close()
+
+
+def test_small_served_mix_matches_single_runs():
+    lbm = _lbm()
+    from paper_2605_30878_amd import serve
+
+    reqs = serve.mixed_requests(12, seed=3, step_scale=0.01, size_scale=0.3, precision=W.FP32)
+    reqs = serve.poisson_arrivals(reqs, rate=200.0, seed=4)
+    srv = serve.Server(hbm_budget=8e9, max_slots=6, tick_steps=40, keep_state=True)
+    res = srv.run(reqs)
+    srv.close()
+    summ = serve.summarize(res, max(r.finished for r in res))
+    print(f"[serve] {summ}", flush=True)
+    assert len(res) == len(reqs)
+    assert all(r.obs["nonfinite"] == 0 for r in res)
+    assert all(r.latency >= 0 and r.obs["step"] == r.steps for r in res)
+    for r in res[:4]:
+        wl = reqs[r.rid].workload
+        s = lbm.Simulation(wl, W.initial_phi(wl))
+        s.step(r.steps)
+        assert np.array_equal(s.read(lbm.FIELD_N), r.state["N"]), wl.name
+        assert np.array_equal(s.read(lbm.FIELD_B), r.state["B"]), wl.name
+        s.close()

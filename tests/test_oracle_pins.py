@@ -334,3 +334,17 @@ def test_no_recolouring_outside_unit_interval(lattice):
         phi_nb = np.full(s.Q, shift) + 1e-6 * rng.normal(size=s.Q)
         Ns, Bs, m = s.node(N, phi_nb)
         assert np.array_equal(Bs, m["phi"] * Ns)
+
+
+def test_fakhari_rule_literal_form_and_neutral_limit():
+    """Eq. 10 as printed, (2/eps)(1 + eps/2 - sqrt((1 + eps/2)^2 - 2 eps phi)) - phi,
+    evaluated where it is well conditioned, equals the oracle's rule; near
+    eps = 0 the oracle's rule is smooth and tends to phi (the neutral angle)."""
+    for phiF in np.linspace(0.0, 1.0, 11):
+        for eps in (-1.0, -0.5, -0.2, 0.2, 0.5, 1.0):
+            a = 1 + eps / 2
+            lit = 2 / eps * (a - math.sqrt(a * a - 2 * eps * phiF)) - phiF
+            assert abs(oracle.ghost_rule(phiF, eps, 1) - lit) < 1e-14
+        for eps in (1e-17, -4.9e-17, 1e-9, -1e-9):
+            assert abs(oracle.ghost_rule(phiF, eps, 1) - phiF) < 1e-8
+        assert oracle.ghost_rule(phiF, 0.0, 1) == phiF
