@@ -35,7 +35,7 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
+def measured_traffic(kernel: str, workload: str):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     counter summary, or None when the kernel source changed since."""
     try:
@@ -43,7 +43,7 @@ def measured_traffic(workload: str):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    rec = t.get("kernels", {}).get("k_collide_stream", {}).get(workload)
+    rec = t.get("kernels", {}).get(kernel, {}).get(workload)
     if not rec or rec.get("kernel_source_hash") != kernel_source_hash():
         return None
     return rec.get("hbm_bytes_per_launch")
@@ -76,10 +76,17 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--size", type=int, default=256)
+    ap.add_argument("--workload", choices=["sphere", "porous"], default="sphere",
+                    help="sphere: drop on a sphere (default); porous: 384^3 random sphere packing, "
+                         "porosity 0.40, theta 45, body force 1e-6")
     ap.add_argument("--theta", type=float, default=90.0)
     ap.add_argument("--precision", choices=["f32", "f64", "f16ofs", "bf16ofs"], default="f32")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-mix latency measurement")
+    ap.add_argument("--fused", action="store_true", help="use the fused one-launch D3Q19 step")
+    ap.add_argument("--full-mix", action="store_true",
+                    help="served mix at full size: 256 requests, 2000-20000 steps each")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (for HBM counter calibration)")
     args = ap.parse_args()
@@ -104,8 +111,11 @@ def main() -> int:
     from paper_2605_30878_amd import workloads as W
 
     prec = {"f32": W.FP32, "f64": W.FP64, "f16ofs": W.FP16_OFS, "bf16ofs": W.BF16_OFS}[args.precision]
-    wl = W.sphere_d3q19(args.size, theta=args.theta, precision=prec)
-    sim = lbm.Simulation(wl, W.initial_phi(wl), device="cuda:0")
+    if args.workload == "porous":
+        wl = W.porous_d3q19(n=384 if args.size == 256 else args.size, precision=prec)
+    else:
+        wl = W.sphere_d3q19(args.size, theta=args.theta, precision=prec)
+    sim = lbm.Simulation(wl, W.initial_phi(wl), device="cuda:0", options=lbm.OPT_FUSED if args.fused else 0)
     obs0 = sim.observe()
     sim.step(args.warmup)
     torch.cuda.synchronize()
@@ -122,21 +132,29 @@ def main() -> int:
     s_t = 8 if prec == W.FP64 else 4            # bytes of phi, G, p
     Q, D = 19, 3
     mlups = wl.nodes * args.steps / (dt * 1e6)
-    # algorithmic bytes of one fused collide-stream launch: per fluid node N
-    # read and N* written (2 Q s_n), phi read once, the compact liquid record
-    # (G, p) written ((D + 1) s_t); one flag byte per box node
-    alg_bytes = n_fluid * (2 * Q * s_n + s_t + (D + 1) * s_t) + wl.nodes
+    fused = args.fused and wl.shape[0] % 32 == 0 and wl.shape[1] % 8 == 0 and wl.shape[2] >= 3
+    if fused:
+        # one fused launch per step: per fluid node N read and N* written
+        # (2 Q s_n), the compact record (phi, G, p) read and written
+        # (2 (D + 2) s_t); one flag byte per box node
+        alg_bytes = n_fluid * (2 * Q * s_n + 2 * (D + 2) * s_t) + wl.nodes
+        impl_bytes = 2 * Q * s_n + 2 * (D + 2) * s_t
+        kernel = "k_step_fused"
+    else:
+        # collide-stream launch: N read and N* written (2 Q s_n), phi read
+        # once, the record (G, p) written ((D + 1) s_t); one flag byte per node
+        alg_bytes = n_fluid * (2 * Q * s_n + s_t + (D + 1) * s_t) + wl.nodes
+        # colour launch (N, phi_prev, record in; phi out) + collide launch
+        impl_bytes = (Q * s_n + 2 * s_t + (D + 1) * s_t) + (2 * Q * s_n + s_t + (D + 1) * s_t)
+        kernel = "k_collide_stream"
     k_ms = ms["collide"] / args.steps
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
-    workload_key = f"d3q19_sphere_{args.size}_{args.precision}"
-    traffic = measured_traffic(workload_key)
+    workload_key = f"d3q19_{args.workload}_{wl.shape[0]}_{args.precision}"
+    traffic = measured_traffic(kernel, workload_key)
     # paper-state bytes per lattice update: N and B read once and written once
     step_bytes = 4 * Q * s_n
-    # this implementation: colour kernel (N, phi_prev, record in; phi out) +
-    # fused kernel (N, phi in; N, record out)
-    impl_bytes = (Q * s_n + 2 * s_t + (D + 1) * s_t) + (2 * Q * s_n + s_t + (D + 1) * s_t)
     result = {
-        "metric": "D3Q19 two-phase MLUPS & % HBM roofline",
+        "metric": "D3Q19 two-phase MLUPS & % HBM roofline; p50/p99 job latency on served mix",
         "value": round(mlups, 2),
         "unit": "MLUPS",
         "n_gpus": 1,
@@ -148,14 +166,20 @@ def main() -> int:
         "vs_baseline": None,
         "dtype": args.precision,
         "data": "synthetic (analytic sphere and tanh drop, deterministic)",
-        "config": {"workload": f"D3Q19 drop on sphere {args.size}^3", "lattice": "D3Q19",
-                   "box": [args.size] * 3, "sphere_radius": 48 * args.size / 256,
-                   "drop_radius": 40 * args.size / 256, "rho_ratio": 1000, "mu_ratio": 100,
-                   "theta_deg": args.theta, "W": 4.0, "sigma": 0.01, "storage": args.precision,
-                   "n_fluid": n_fluid, "n_ghost": obs1["n_ghost"]},
+        "config": ({"workload": f"D3Q19 drop on sphere {args.size}^3", "lattice": "D3Q19",
+                    "box": [args.size] * 3, "sphere_radius": 48 * args.size / 256,
+                    "drop_radius": 40 * args.size / 256, "rho_ratio": 1000, "mu_ratio": 100,
+                    "theta_deg": args.theta, "W": 4.0, "sigma": 0.01, "storage": args.precision,
+                    "n_fluid": n_fluid, "n_ghost": obs1["n_ghost"]} if args.workload == "sphere" else
+                   {"workload": f"D3Q19 porous packing {wl.shape[0]}^3", "lattice": "D3Q19",
+                    "box": list(wl.shape), "spheres": len(wl.solids), "sphere_radius": 12, "rho_ratio": 10,
+                    "mu_ratio": 10, "theta_deg": 45, "body_accel": 1e-6, "storage": args.precision,
+                    "n_fluid": n_fluid, "n_ghost": obs1["n_ghost"],
+                    "porosity_nodes": round(n_fluid / wl.nodes, 4),
+                    "mflups": round(n_fluid * args.steps / (dt * 1e6), 2)}),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_collide_stream", "alg_bytes_per_launch": alg_bytes,
+                     "kernel": kernel, "alg_bytes_per_launch": alg_bytes,
                      "avg_launch_ms": round(k_ms, 5)},
         "step_roofline": {"bytes_per_update": step_bytes, "impl_bytes_per_update": impl_bytes,
                           "roofline_mlups": round(HBM_PEAK_GBS * 1e9 / step_bytes / 1e6, 1),
@@ -167,6 +191,30 @@ def main() -> int:
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    if not args.no_serve:
+        from paper_2605_30878_amd import serve
+
+        count, scale = (256, 1.0) if args.full_mix else (64, 0.1)
+        mix = serve.serve_mix(count=count, step_scale=scale, precision=W.FP32)
+        mix16 = serve.serve_mix(count=count, step_scale=scale, precision=W.FP16_OFS)
+        result["served_mix"] = {
+            "requests": count, "steps": "U(2000, 20000) x %g" % scale,
+            "f32": {"p50_s": round(mix["open_loop"]["p50_latency_s"], 4),
+                    "p99_s": round(mix["open_loop"]["p99_latency_s"], 4),
+                    "throughput_jobs_s": round(mix["open_loop"]["throughput_jobs_s"], 3),
+                    "aggregate_mlups": round(mix["open_loop"]["aggregate_mlups"], 1),
+                    "arrival_rate_jobs_s": round(mix["arrival_rate_jobs_s"], 3),
+                    "closed_loop_mlups": round(mix["closed_loop"]["aggregate_mlups"], 1),
+                    "nonfinite_jobs": mix["nonfinite_jobs"]},
+            "f16ofs": {"p50_s": round(mix16["open_loop"]["p50_latency_s"], 4),
+                       "p99_s": round(mix16["open_loop"]["p99_latency_s"], 4),
+                       "throughput_jobs_s": round(mix16["open_loop"]["throughput_jobs_s"], 3),
+                       "aggregate_mlups": round(mix16["open_loop"]["aggregate_mlups"], 1),
+                       "arrival_rate_jobs_s": round(mix16["arrival_rate_jobs_s"], 3),
+                       "closed_loop_mlups": round(mix16["closed_loop"]["aggregate_mlups"], 1),
+                       "nonfinite_jobs": mix16["nonfinite_jobs"]},
+        }
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(wl, args.cpu_steps)
     print(json.dumps(result), flush=True)

@@ -57,6 +57,14 @@ enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
 /* Population storage.  Arithmetic is FP64 for LBM_FP64 and FP32 otherwise. */
 enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_OFS = 2, LBM_BF16_OFS = 3 };
 
+/* Step forms.  By default every step is three launches: colour field,
+ * ghost update, fused collide-stream.  With LBM_OPT_FUSED, D3Q19 boxes with
+ * n[0] % 32 == 0, n[1] % 8 == 0 and n[2] >= 3 run each step (except the first
+ * after an initial state or a restore) as a ghost pre-pass plus one launch
+ * over 32 x 8 x z tiles that forms phi of the tile and a one-node ring in LDS
+ * and reads N once.  Both compute the same update. */
+#define LBM_OPT_FUSED 1
+
 /* Ghost-node rule: Eq. 9 (this paper) or Eq. 10 (Fakhari et al.). */
 enum { LBM_GHOST_EQ9 = 0, LBM_GHOST_FAKHARI = 1 };
 
@@ -86,7 +94,7 @@ typedef struct {
     uint32_t precision;     /* LBM_FP64 ... */
     uint32_t ghost_rule;    /* LBM_GHOST_EQ9 or LBM_GHOST_FAKHARI */
     int32_t n[3];           /* box nodes; n[2] must be 1 for D2Q9 */
-    int32_t pad;
+    int32_t options;        /* bit 0 (LBM_OPT_FUSED): use the fused one-launch D3Q19 step where it applies */
     double rho_l, rho_g;    /* liquid (phi = 1) and gas (phi = 0) densities, > 0 */
     double mu_l, mu_g;      /* dynamic viscosities, > 0 */
     double sigma;           /* surface tension, >= 0 */

@@ -369,6 +369,7 @@ int lbm_bind(lbm_ctx* c, void* dev, size_t bytes, void* stream) {
     d.result = (double*)p; p += align256(8 * 8);
     d.nonfinite = (int64_t*)p; p += align256((size_t)(REDUCE_BLOCKS + 1) * 8);
     d.n_ghost = (int32_t)ng;
+    d.fused = (c->P.options & LBM_OPT_FUSED) ? 1 : 0;
     // Upload the geometry.
     hipStream_t st = c->stream;
     HIPCHK(c, hipMemcpyAsync(d.flags, c->flags.data(), (size_t)c->n, hipMemcpyHostToDevice, st), "upload flags");
@@ -629,7 +630,7 @@ struct lbm_batch {
     char* table = nullptr;
     size_t bytes = 0;
     hipStream_t stream = nullptr;
-    std::vector<char> staging[4];
+    std::vector<char> staging[8];   // one per (lattice, precision) group
     std::string err;
 };
 
@@ -704,10 +705,10 @@ int lbm_batch_step(lbm_batch* b, lbm_ctx* const* ctxs, const int64_t* steps, int
                 sorted.push_back(jobs[k]);
                 nsteps = std::max(nsteps, jobs[k].steps);
             }
-            const size_t need = batch_table_bytes((int)sorted.size());
+            const size_t need = batch_group_bytes((int)sorted.size());
             if (off + need > b->bytes) return bfail(b, LBM_ENOMEM, "batch table too small for this many jobs");
             e = launch_batch((int)lat, prec, sorted.data(), (int)sorted.size(), b->table + off, need, nsteps, b->stream,
-                             b->staging[group & 3]);
+                             b->staging[group]);
             if (e != hipSuccess) return bfail(b, LBM_EHIP, std::string("batch launch: ") + hipGetErrorString(e));
             off += need;
             group++;
@@ -723,7 +724,6 @@ int lbm_batch_step(lbm_batch* b, lbm_ctx* const* ctxs, const int64_t* steps, int
             }
         }
     }
-    if (group > 4) return bfail(b, LBM_EINVAL, "internal: more than four groups");
     return LBM_OK;
 }
 

@@ -345,6 +345,21 @@ __device__ __forceinline__ bool row_index(int nx, int ny, RowIdx& r) {
     return true;
 }
 
+// One term of the compact liquid population: phi(src) N_i(y) +
+// sgn (c_i . G(src)) (chi_i + w_i p(src) / cs^2); components of G along
+// zero components of c_i are not used.
+template <class L, class T, int I>
+__device__ __forceinline__ T compact_term(T n, T phi_src, T gx, T gy, T gz, T p, T sgn,
+                                          const KParams<T, L::Q>& P) {
+    constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
+    constexpr T wi = T(L::w[I]);
+    T cG = T(0);
+    if constexpr (cx != 0) cG += cmul<cx>(gx);
+    if constexpr (cy != 0) cG += cmul<cy>(gy);
+    if constexpr (cz != 0) cG += cmul<cz>(gz);
+    return phi_src * n + sgn * cG * (P.chi[I] + wi * T(3) * p);
+}
+
 // Post-stream liquid population B_i(y) from the compact record.  nb[i] is
 // y + c_i, so the source y - c_i is nb[opp(i)]; at a bounce-back link the
 // source is y with c_i reversed.
@@ -359,19 +374,16 @@ __device__ __forceinline__ T compact_B(const SN* __restrict__ N, const T* __rest
         return phi_prev[y] * n;
     } else {
         constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
-        constexpr T wi = T(L::w[I]);
         int64_t src = nb[L::opp[I]];
         T sgn = T(1);
         if (near_solid && (flags[src] & FLAG_SOLID)) {
             src = y;
             sgn = T(-1);
         }
-        T cG = T(0);
-        if constexpr (cx != 0) cG += cmul<cx>(G[src]);
-        if constexpr (cy != 0) cG += cmul<cy>(G[S + src]);
-        if constexpr (cz != 0) cG += cmul<cz>(G[2 * S + src]);
-        const T p = G[(int64_t)GRec<L>::P * S + src];
-        return phi_prev[src] * n + sgn * cG * (P.chi[I] + wi * T(3) * p);
+        const T gx = cx != 0 ? G[src] : T(0);
+        const T gy = cy != 0 ? G[S + src] : T(0);
+        const T gz = cz != 0 ? G[2 * S + src] : T(0);
+        return compact_term<L, T, I>(n, phi_prev[src], gx, gy, gz, G[(int64_t)GRec<L>::P * S + src], sgn, P);
     }
 }
 
@@ -760,6 +772,242 @@ __global__ __launch_bounds__(256) void k_solid_in(const double* __restrict__ src
     }
 }
 
+// ------------------------------------------------------------------ fused D3Q19 step
+// One launch per step (after the ghost pre-pass) for D3Q19 boxes whose x and
+// y extents are multiples of the tile: every workgroup owns a 32 x 8 column
+// of nodes and marches up a chunk of z-planes.  For each plane it forms
+// phi^{n+1} = sum_i B_i on the tile and a one-node ring from the compact
+// record (staged in LDS for the tile and two rings, three planes deep), then
+// collides the plane below from registers: each node's N is read from HBM
+// once per step (the ring's N comes from L2), phi^{n+1} never leaves the
+// workgroup except as next step's record.  Arithmetic per node is the same
+// as the colour and fused kernels of the two-launch step.
+constexpr int FTX = 32, FTY = 8;                 // tile
+constexpr int FRX = FTX + 2, FRY = FTY + 2;      // tile + 1 ring (phi window)
+constexpr int FSX = FTX + 4, FSY = FTY + 4;      // tile + 2 rings (record window)
+constexpr int FKS = 5;                           // phi_prev, Gx, Gy, Gz, p
+
+__device__ __forceinline__ int wrapc(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+__device__ __forceinline__ int slot3(int z) { return (z % 3 + 3) % 3; }
+
+// Ghost pre-pass of the fused step: like k_ghost, but the fluid corners'
+// phi^{n+1} are formed here from the compact record (the colour field of
+// this step is not stored anywhere else).
+template <class L, class T, class SN>
+__global__ __launch_bounds__(256) void k_ghost_direct(const int32_t* __restrict__ g_node,
+                                                      const int32_t* __restrict__ g_corner,
+                                                      const T* __restrict__ g_w, const uint8_t* __restrict__ g_mask,
+                                                      int ng, const SN* __restrict__ N, const T* __restrict__ phiA,
+                                                      const T* __restrict__ G, const uint8_t* __restrict__ flags,
+                                                      T* __restrict__ phiB, T E, T eps, int rule,
+                                                      KParams<T, L::Q> P) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= ng) return;
+    const uint32_t mask = g_mask[g];
+    T f = 0;
+#pragma unroll 1
+    for (int k = 0; k < L::NC; k++) {
+        const int32_t c = g_corner[(int64_t)k * ng + g];
+        T v;
+        if ((mask >> k) & 1u) {
+            v = phiA[c];
+        } else {
+            const int ix = c % P.nx, iy = (c / P.nx) % P.ny, iz = c / (P.nx * P.ny);
+            int64_t nb[L::Q];
+            neighbours<L>(ix, iy, iz, P.nx, P.ny, P.nz, nb);
+            const bool near = (flags[c] & FLAG_NEAR_SOLID) != 0;
+            T acc = 0;
+            static_for<0, L::Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                acc += compact_B<L, T, SN, i>(N, phiA, G, flags, P, c, nb, near);
+            });
+            v = acc;
+        }
+        f += g_w[(int64_t)k * ng + g] * v;
+    }
+    T out;
+    if (rule == 0) {
+        out = f / (f + (T(1) - f) * E);
+    } else {
+        const T a = T(1) + T(0.5) * eps;
+        out = T(4) * f / (a + sqrt(a * a - T(2) * eps * f)) - f;
+    }
+    phiB[g_node[g]] = out;
+}
+
+template <class T, class SN>
+struct FusedSmem {
+    T rec[3][FKS][FSY][FSX];   // record window: planes by slot3(z)
+    uint8_t fl[3][FSY][FSX];   // flags of the same nodes
+    T phi[3][FRY][FRX];        // phi^{n+1} window: planes by slot3(z)
+};
+
+// Stage the record and flags of plane z (tile + two rings) into LDS.
+template <class T, class SN>
+__device__ __forceinline__ void fused_load_plane(FusedSmem<T, SN>& sm, int z, int x0, int y0,
+                                                 const T* __restrict__ phiA, const T* __restrict__ G,
+                                                 const uint8_t* __restrict__ flags, const KParams<T, 19>& P) {
+    const int s = slot3(z);
+    const int Z = wrapc(z, P.nz);
+    const int64_t S = P.S;
+    for (int k = threadIdx.x; k < FSX * FSY; k += FTX * FTY) {
+        const int lx = k % FSX, ly = k / FSX;
+        const int X = wrapc(x0 + lx - 2, P.nx), Y = wrapc(y0 + ly - 2, P.ny);
+        const int64_t id = (int64_t)X + (int64_t)P.nx * ((int64_t)Y + (int64_t)P.ny * Z);
+        sm.rec[s][0][ly][lx] = phiA[id];
+        sm.rec[s][1][ly][lx] = G[id];
+        sm.rec[s][2][ly][lx] = G[S + id];
+        sm.rec[s][3][ly][lx] = G[2 * S + id];
+        sm.rec[s][4][ly][lx] = G[3 * S + id];
+        sm.fl[s][ly][lx] = flags[id];
+    }
+}
+
+// phi^{n+1} of one node of plane z at tile-local (lx, ly) in [-1, FTX] x
+// [-1, FTY]; N of the node is returned (decoded) for reuse.
+template <class T, class SN>
+__device__ __forceinline__ T fused_phi_node(const FusedSmem<T, SN>& sm, int z, int lx, int ly, int64_t id,
+                                            const SN* __restrict__ N, const T* __restrict__ phiB,
+                                            const KParams<T, 19>& P, T (&n)[19]) {
+    using L = LatD3Q19;
+    const int sx = lx + 2, sy = ly + 2;
+    const uint8_t f = sm.fl[slot3(z)][sy][sx];
+    if (f & FLAG_SOLID) return phiB[id];
+    const bool near = (f & FLAG_NEAR_SOLID) != 0;
+    T acc = 0;
+    static_for<0, L::Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+        n[i] = NStore<T, SN>::dec(N[(int64_t)i * P.S + id], P.chi[i], P.n_s);
+        if constexpr (i == 0) {
+            acc += sm.rec[slot3(z)][0][sy][sx] * n[0];
+        } else {
+            int s = slot3(z - cz), qx = sx - cx, qy = sy - cy;
+            T sgn = T(1);
+            if (near && (sm.fl[s][qy][qx] & FLAG_SOLID)) {
+                s = slot3(z);
+                qx = sx;
+                qy = sy;
+                sgn = T(-1);
+            }
+            acc += compact_term<L, T, i>(n[i], sm.rec[s][0][qy][qx], sm.rec[s][1][qy][qx], sm.rec[s][2][qy][qx],
+                                         sm.rec[s][3][qy][qx], sm.rec[s][4][qy][qx], sgn, P);
+        }
+    });
+    return acc;
+}
+
+// Form phi^{n+1} of plane z on the tile and its ring into the phi window;
+// the thread's own tile node keeps its N in `mine`.  Tile values inside the
+// chunk are also written to phiB (next step's record).
+template <class T, class SN>
+__device__ __forceinline__ void fused_form_plane(FusedSmem<T, SN>& sm, int z, int z0, int z1, int x0, int y0,
+                                                 const SN* __restrict__ N, T* __restrict__ phiB,
+                                                 const KParams<T, 19>& P, T (&mine)[19]) {
+    const int tx = threadIdx.x % FTX, ty = threadIdx.x / FTX;
+    const int Z = wrapc(z, P.nz);
+    const int sp = slot3(z);
+    {
+        const int X = x0 + tx, Y = y0 + ty;
+        const int64_t id = (int64_t)X + (int64_t)P.nx * ((int64_t)Y + (int64_t)P.ny * Z);
+        const T v = fused_phi_node<T, SN>(sm, z, tx, ty, id, N, phiB, P, mine);
+        sm.phi[sp][ty + 1][tx + 1] = v;
+        if (z >= z0 && z < z1 && !(sm.fl[sp][ty + 2][tx + 2] & FLAG_SOLID)) phiB[id] = v;
+    }
+    // ring: 2 (FTX + 2) + 2 FTY nodes, one per thread
+    constexpr int NR = 2 * (FTX + 2) + 2 * FTY;
+    const int r = threadIdx.x;
+    if (r < NR) {
+        int lx, ly;
+        if (r < FTX + 2) { lx = r - 1; ly = -1; }
+        else if (r < 2 * (FTX + 2)) { lx = r - (FTX + 2) - 1; ly = FTY; }
+        else if (r < 2 * (FTX + 2) + FTY) { lx = -1; ly = r - 2 * (FTX + 2); }
+        else { lx = FTX; ly = r - 2 * (FTX + 2) - FTY; }
+        const int X = wrapc(x0 + lx, P.nx), Y = wrapc(y0 + ly, P.ny);
+        const int64_t id = (int64_t)X + (int64_t)P.nx * ((int64_t)Y + (int64_t)P.ny * Z);
+        T scratch[19];
+        sm.phi[sp][ly + 1][lx + 1] = fused_phi_node<T, SN>(sm, z, lx, ly, id, N, phiB, P, scratch);
+    }
+}
+
+template <class T, class SN>
+__global__ __launch_bounds__(FTX * FTY) void k_step_fused(const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
+                                                          const T* __restrict__ phiA, T* __restrict__ phiB,
+                                                          const T* __restrict__ Gsrc, T* __restrict__ Gdst,
+                                                          const uint8_t* __restrict__ flags, KParams<T, 19> P,
+                                                          int zc) {
+    using L = LatD3Q19;
+    constexpr int Q = 19;
+    __shared__ FusedSmem<T, SN> sm;
+    const int x0 = blockIdx.x * FTX, y0 = blockIdx.y * FTY;
+    const int z0 = blockIdx.z * zc;
+    const int z1 = min(z0 + zc, P.nz);
+    const int tx = threadIdx.x % FTX, ty = threadIdx.x / FTX;
+    T ncur[Q], nnext[Q];
+    // prologue: phi of planes z0 - 1 and z0
+    fused_load_plane<T, SN>(sm, z0 - 2, x0, y0, phiA, Gsrc, flags, P);
+    fused_load_plane<T, SN>(sm, z0 - 1, x0, y0, phiA, Gsrc, flags, P);
+    fused_load_plane<T, SN>(sm, z0, x0, y0, phiA, Gsrc, flags, P);
+    __syncthreads();
+    fused_form_plane<T, SN>(sm, z0 - 1, z0, z1, x0, y0, Nsrc, phiB, P, nnext);
+    __syncthreads();
+    fused_load_plane<T, SN>(sm, z0 + 1, x0, y0, phiA, Gsrc, flags, P);
+    __syncthreads();
+    fused_form_plane<T, SN>(sm, z0, z0, z1, x0, y0, Nsrc, phiB, P, ncur);
+    for (int z = z0; z < z1; z++) {
+        __syncthreads();
+        fused_load_plane<T, SN>(sm, z + 2, x0, y0, phiA, Gsrc, flags, P);
+        __syncthreads();
+        fused_form_plane<T, SN>(sm, z + 1, z0, z1, x0, y0, Nsrc, phiB, P, nnext);
+        __syncthreads();
+        // collide plane z at the thread's node
+        const int sz = slot3(z);
+        if (!(sm.fl[sz][ty + 2][tx + 2] & FLAG_SOLID)) {
+            const int ix = x0 + tx, iy = y0 + ty, iz = z;
+            const int64_t x = (int64_t)ix + (int64_t)P.nx * ((int64_t)iy + (int64_t)P.ny * iz);
+            const uint8_t f = sm.fl[sz][ty + 2][tx + 2];
+            T ph[Q];
+            static_for<0, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+                ph[i] = sm.phi[slot3(z + cz)][ty + 1 + cy][tx + 1 + cx];
+            });
+            Macro<T> m;
+            T Pi[6];
+            macro_stage<L, T>(ncur, ph, P, m, Pi);
+            T Ns[Q], Gv[3];
+            collide_stage<L, T>(m, Pi, P, Ns, Gv);
+            using NS = NStore<T, SN>;
+            SN e[Q];
+            T closure = P.n_close;
+#pragma unroll
+            for (int i = 1; i < Q; i++) {
+                e[i] = NS::enc(Ns[i], P.chi[i], P.n_inv_s);
+                closure -= NS::off(e[i]);
+            }
+            e[0] = NS::enc_off(closure);
+            int64_t nb[Q];
+            neighbours<L>(ix, iy, iz, P.nx, P.ny, P.nz, nb);
+            const int64_t S = P.S;
+            if (f & FLAG_NEAR_SOLID) {
+                static_for<0, Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    if (flags[nb[i]] & FLAG_SOLID) Ndst[(int64_t)L::opp[i] * S + x] = e[i];
+                    else Ndst[(int64_t)i * S + nb[i]] = e[i];
+                });
+            } else {
+#pragma unroll
+                for (int i = 0; i < Q; i++) Ndst[(int64_t)i * S + nb[i]] = e[i];
+            }
+#pragma unroll
+            for (int a = 0; a < 3; a++) Gdst[(int64_t)a * S + x] = Gv[a];
+            Gdst[3 * S + x] = m.p;
+        }
+#pragma unroll
+        for (int i = 0; i < Q; i++) ncur[i] = nnext[i];
+    }
+}
+
 // ------------------------------------------------------------------ batched steps
 // Many independent runs advance in shared launches: every workgroup (one
 // wave, 64 threads) finds its job by binary search over the jobs' first
@@ -858,9 +1106,52 @@ static inline int row_block(int nx) {
     return b > LBM_COLLIDE_BX ? LBM_COLLIDE_BX : b;
 }
 
+// The fused one-launch step applies to D3Q19 boxes tiled exactly by 32 x 8
+// columns with at least 3 planes, once the liquid state is the compact record.
+static inline bool fused_ok(int lattice, const StepParams& p, int from_planes) {
+    // (opt-in: the workgroup-serial z-march is latency-bound on gfx950)
+    return lattice == 1 && !from_planes && p.nx % FTX == 0 && p.ny % FTY == 0 && p.nz >= 3;
+}
+
+// z-chunk of the fused step: about 1024 workgroups, at least 4 planes each.
+static inline int fused_chunk(const StepParams& p) {
+    const int64_t cols = (int64_t)(p.nx / FTX) * (p.ny / FTY);
+    int64_t zc = (p.nz * cols + 1023) / 1024;
+    if (zc < 4) zc = 4;
+    if (zc > p.nz) zc = p.nz;
+    return (int)zc;
+}
+
+template <class L, class T, class SN>
+static hipError_t fused_phase_t(int phase, const DevState& d, const StepParams& p, int cur, int ps,
+                                hipStream_t st) {
+    if constexpr (L::D == 3) {
+        const KParams<T, L::Q> kp = make_kparams<T, L, SN>(p);
+        T* work = (T*)d.phi[1 - ps];
+        if (phase == 1 && d.n_ghost > 0) {
+            hipLaunchKernelGGL((k_ghost_direct<L, T, SN>), dim3(blocks_for(d.n_ghost, 256)), dim3(256), 0, st,
+                               d.g_node, d.g_corner, (const T*)d.g_w, d.g_mask, d.n_ghost, (const SN*)d.N[cur],
+                               (const T*)d.phi[ps], (const T*)d.G[cur], d.flags, work, (T)p.exp_eps, (T)p.eps,
+                               p.ghost_rule, kp);
+        } else if (phase == 2) {
+            const int zc = fused_chunk(p);
+            const dim3 grid((unsigned)(p.nx / FTX), (unsigned)(p.ny / FTY), (unsigned)((p.nz + zc - 1) / zc));
+            hipLaunchKernelGGL((k_step_fused<T, SN>), grid, dim3(FTX * FTY), 0, st, (const SN*)d.N[cur],
+                               (SN*)d.N[1 - cur], (const T*)d.phi[ps], work, (const T*)d.G[cur], (T*)d.G[1 - cur],
+                               d.flags, kp, zc);
+        }
+        return hipGetLastError();
+    } else {
+        (void)phase; (void)d; (void)p; (void)cur; (void)ps; (void)st;
+        return hipErrorNotSupported;
+    }
+}
+
 template <class L, class T, class SN>
 static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int cur, int ps, int from_planes,
-                          hipStream_t st) {
+                          hipStream_t st, bool allow_fused = true) {
+    if (allow_fused && d.fused && fused_ok(L::D == 3 ? 1 : 0, p, from_planes))
+        return fused_phase_t<L, T, SN>(phase, d, p, cur, ps, st);
     T* work = (T*)d.phi[1 - ps];
     const int bx = row_block(p.nx);
     if (phase == 0) {
@@ -889,9 +1180,9 @@ static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int
 template <class L, class T, class SN>
 static hipError_t colour_t(const DevState& d, const StepParams& p, int cur, int ps, int from_planes,
                            hipStream_t st) {
-    hipError_t e = phase_t<L, T, SN>(0, d, p, cur, ps, from_planes, st);
+    hipError_t e = phase_t<L, T, SN>(0, d, p, cur, ps, from_planes, st, false);
     if (e != hipSuccess) return e;
-    return phase_t<L, T, SN>(1, d, p, cur, ps, from_planes, st);
+    return phase_t<L, T, SN>(1, d, p, cur, ps, from_planes, st, false);
 }
 
 template <class L, class T, class SN>
@@ -1027,10 +1318,10 @@ hipError_t launch_plane_in(int lattice, uint32_t prec, const DevState& d, const 
                            int cur, hipStream_t st) {
     LBM_DISPATCH(plane_in_t, d, p, which, dir, cur, st);
 }
-size_t batch_table_bytes(int max_jobs) {
-    size_t per = sizeof(BJob<LatD3Q19, double, double>) + 2 * sizeof(int64_t);
-    return (size_t)max_jobs * per + 16 * 256;
-}
+// Per job: the descriptor and two block offsets; per group: alignment slack.
+static size_t batch_job_bytes() { return sizeof(BJob<LatD3Q19, double, double>) + 2 * sizeof(int64_t); }
+size_t batch_group_bytes(int njobs) { return (size_t)njobs * batch_job_bytes() + 1024; }
+size_t batch_table_bytes(int max_jobs) { return (size_t)max_jobs * batch_job_bytes() + 8 * 1024; }
 
 template <class L, class T, class SN>
 static hipError_t batch_t(const BatchJobHost* jobs, int nj, void* table, size_t table_bytes, int64_t nsteps,

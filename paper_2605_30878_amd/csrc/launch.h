@@ -44,6 +44,7 @@ struct DevState {
     double* partial;    // [REDUCE_BLOCKS][8] reduction partials
     double* result;     // [8] reduced diagnostics
     int64_t* nonfinite; // [REDUCE_BLOCKS + 1]
+    int32_t fused;      // 1: D3Q19 steps use the fused one-launch form where the box allows it (opt-in)
 };
 
 constexpr int REDUCE_BLOCKS = 1024;
@@ -94,8 +95,10 @@ struct BatchJobHost {
     int64_t steps;
 };
 
-// Device bytes of a batch job table for up to max_jobs jobs (all groups).
+// Device bytes of a batch job table for up to max_jobs jobs (all groups),
+// and of one (lattice, precision) group of njobs jobs.
 size_t batch_table_bytes(int max_jobs);
+size_t batch_group_bytes(int njobs);
 // Advance every job of one (lattice, precision) group by its `steps`
 // (<= nsteps) with one launch per phase and sub-step for the whole group.
 // Jobs must be sorted by steps, largest first.  The table is uploaded from

@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 ABI_VERSION = 1
 OK, EINVAL, ESTATE, ENOMEM, EHIP, EUNSTABLE = 0, -1, -2, -3, -4, -5
+OPT_FUSED = 1
 FIELD_PHI, FIELD_N, FIELD_B, FIELD_U, FIELD_P, FIELD_SOLID_PHI, FIELD_FLAGS = range(7)
 FLAG_SOLID, FLAG_NEAR_SOLID, FLAG_GHOST = 1, 2, 4
 
@@ -36,7 +37,7 @@ class LbmError(RuntimeError):
 
 class lbm_params(C.Structure):
     _fields_ = [("abi_version", C.c_uint32), ("lattice", C.c_uint32), ("precision", C.c_uint32),
-                ("ghost_rule", C.c_uint32), ("n", C.c_int32 * 3), ("pad", C.c_int32),
+                ("ghost_rule", C.c_uint32), ("n", C.c_int32 * 3), ("options", C.c_int32),
                 ("rho_l", C.c_double), ("rho_g", C.c_double), ("mu_l", C.c_double), ("mu_g", C.c_double),
                 ("sigma", C.c_double), ("W", C.c_double), ("mobility", C.c_double),
                 ("body_accel", C.c_double * 3)]
@@ -104,8 +105,9 @@ def lattice(lat: int) -> np.ndarray:
     return np.array(c[: 3 * q.value], dtype=np.int64).reshape(q.value, 3)
 
 
-def make_params(wl: W.Workload) -> lbm_params:
+def make_params(wl: W.Workload, options: int = 0) -> lbm_params:
     p = lbm_params()
+    p.options = int(options)
     p.abi_version = ABI_VERSION
     p.lattice = int(wl.lattice)
     p.precision = int(wl.precision)
@@ -138,7 +140,7 @@ class Simulation:
     -> bind (torch buffer + current stream) -> set_wetting -> set_field(PHI)."""
 
     def __init__(self, wl: W.Workload, phi_init: Optional[np.ndarray] = None, device: str = "cuda:0",
-                 stream=None):
+                 stream=None, options: int = 0):
         import torch
 
         lib = load_library()
@@ -147,7 +149,7 @@ class Simulation:
         self.n = wl.nodes
         self.Q = W.n_directions(wl.lattice)
         h = C.c_void_p()
-        params = make_params(wl)
+        params = make_params(wl, options)
         rc = lib.lbm_create(C.byref(params), C.byref(h))
         if rc != OK:
             raise LbmError(rc, lib.lbm_last_error(None).decode())

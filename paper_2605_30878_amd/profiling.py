@@ -1,0 +1,105 @@
+"""Summaries of rocprofv3 output for profiles/: per-kernel durations from a
+--kernel-trace --stats run, and HBM bytes per dispatch from two --pmc runs
+(FETCH_SIZE, WRITE_SIZE), each scaled by what the same counter reads for a
+plain device copy of known size.
+
+    python -m paper_2605_30878_amd.profiling stats <kernel_stats.csv> <out.md> "<command>"
+    python -m paper_2605_30878_amd.profiling traffic <fetch.csv> <write.csv> <copy_fetch.csv> \
+        <copy_write.csv> <copy_bytes> <workload_key> <out.md> "<commands>"
+"""
+from __future__ import annotations
+
+import csv
+import hashlib
+import json
+import os
+import sys
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+KERNEL_SRC = os.path.join(HERE, "csrc", "kernels.hip")
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+
+
+def kernel_source_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def short_name(name: str) -> str:
+    base = name.split("(")[0]
+    if base.startswith("void "):
+        base = base[5:]
+    return base
+
+
+def stats_markdown(stats_csv: str, command: str) -> str:
+    rows = list(csv.DictReader(open(stats_csv)))
+    lines = ["| kernel | calls | average (us) | min (us) | max (us) | share |", "|---|---|---|---|---|---|"]
+    for r in rows:
+        lines.append(f"| `{short_name(r['Name'])}` | {r['Calls']} | {float(r['AverageNs']) / 1e3:.2f} | "
+                     f"{float(r['MinNs']) / 1e3:.2f} | {float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} % |")
+    return "Command:\n\n```\n" + command + "\n```\n\n" + "\n".join(lines) + "\n"
+
+
+def _counter_means(path: str):
+    acc = defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        acc[short_name(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes: float):
+    """Per-kernel HBM bytes per dispatch, calibrated on the copy kernel
+    (the dispatch with the largest counter value in the copy runs)."""
+    cf = max(_counter_means(copy_fetch_csv).values())
+    cw = max(_counter_means(copy_write_csv).values())
+    f_scale = copy_bytes / (cf * 1024.0)
+    w_scale = copy_bytes / (cw * 1024.0)
+    fetch = _counter_means(fetch_csv)
+    write = _counter_means(write_csv)
+    out = {}
+    for k in fetch:
+        fb = fetch[k] * 1024.0 * f_scale
+        wb = write.get(k, 0.0) * 1024.0 * w_scale
+        out[k] = {"fetch_bytes": fb, "write_bytes": wb, "hbm_bytes_per_launch": fb + wb}
+    return out, f_scale, w_scale
+
+
+def main(argv):
+    if argv[0] == "stats":
+        md = stats_markdown(argv[1], argv[3])
+        with open(argv[2], "w") as f:
+            f.write(md)
+        return 0
+    if argv[0] == "traffic":
+        fetch, write, cfetch, cwrite, cbytes, key, out_md, cmds = argv[1:9]
+        per, fs, ws = traffic(fetch, write, cfetch, cwrite, float(cbytes))
+        h = kernel_source_hash()
+        data = {}
+        if os.path.exists(TRAFFIC_JSON):
+            data = json.load(open(TRAFFIC_JSON))
+        data.setdefault("kernels", {})
+        for k, v in per.items():
+            name = k.split("<")[0].split("::")[-1]
+            data["kernels"].setdefault(name, {})[key] = dict(v, kernel_source_hash=h)
+        data["calibration"] = {"copy_bytes": float(cbytes), "fetch_scale": fs, "write_scale": ws}
+        with open(TRAFFIC_JSON, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        lines = ["Commands:", "", "```", cmds, "```", "",
+                 f"Calibration on a plain device copy of {float(cbytes) / 2**30:.0f} GiB: FETCH_SIZE x {fs:.4f}, "
+                 f"WRITE_SIZE x {ws:.4f} (counters in KiB per dispatch).", "",
+                 f"Kernel source hash: `{h}`", "",
+                 "| kernel | fetch (MB) | write (MB) | HBM bytes per launch (MB) |", "|---|---|---|---|"]
+        for k, v in sorted(per.items(), key=lambda kv: -kv[1]["hbm_bytes_per_launch"]):
+            lines.append(f"| `{k}` | {v['fetch_bytes'] / 1e6:.1f} | {v['write_bytes'] / 1e6:.1f} | "
+                         f"{v['hbm_bytes_per_launch'] / 1e6:.1f} |")
+        with open(out_md, "w") as f:
+            f.write("\n".join(lines) + "\n")
+        return 0
+    raise SystemExit(__doc__)
+
+
+if __name__ == "__main__":
+    sys.exit(main(sys.argv[1:]))

@@ -37,14 +37,20 @@ def measure_state(sim, wl):
     rho = sim.get(oracle.F_RHO)
     c = n / 2.0
     R = wl.solids[0].radius
-    fit = measure.curved_contact_angle(phi, wl.shape, solid, (c, c, c), R, wl.W, dim=3)
     apex = measure.apex_height(phi, wl.shape, (n // 2, n // 2, 0), c + R, axis=2) - c
     ph = rho * p
     fluid = ~solid
     speed = np.sqrt((u * u).sum(axis=0))
-    return {"theta_fit": fit["theta"], "Rc": fit["Rc"], "d": fit["d"], "apex": apex,
-            "dp_h": float(ph[fluid & (phi > 0.999)].mean() - ph[fluid & (phi < 0.001)].mean()),
-            "max_speed": float(speed[fluid].max()), "mass_blue": float(phi[fluid].sum())}
+    mass = float(phi[fluid].sum())
+    rec = {"apex": apex, "theta_apex": measure.angle_from_apex(R, mass, apex, dim=3),
+           "dp_h": float(ph[fluid & (phi > 0.999)].mean() - ph[fluid & (phi < 0.001)].mean()),
+           "max_speed": float(speed[fluid].max()), "mass_blue": mass}
+    try:
+        fit = measure.curved_contact_angle(phi, wl.shape, solid, (c, c, c), R, wl.W, dim=3, margin=1.0)
+        rec.update({"theta_fit": fit["theta"], "Rc": fit["Rc"], "d": fit["d"]})
+    except ValueError:
+        rec.update({"theta_fit": None, "Rc": None, "d": None})
+    return rec
 
 
 def main(thetas):

@@ -1,0 +1,85 @@
+"""Reduced-precision runs of the D3Q19 drop on a sphere (64^3, density ratio
+1000, viscosity ratio 100) against the FP64 oracle after 20000 steps: the
+contact angle (from the apex height and liquid volume, Section 3.2's
+measure) within 0.5 degrees, the spurious-current maximum within 10 %, the
+Laplace pressure jump within 2 %.  The oracle's numbers are in
+tests/golden/sphere64_oracle.json, written by tests/golden/make_sphere64.py
+(oracle only); the same FP64 fit is applied to both."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_2605_30878_amd import measure
+from paper_2605_30878_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sphere64_oracle.json")
+
+
+def _golden():
+    if not os.path.exists(GOLDEN):
+        return {}
+    with open(GOLDEN) as f:
+        return json.load(f)
+
+
+def _measure(lbm, sim, wl):
+    n = wl.shape[0]
+    flags = sim.read(lbm.FIELD_FLAGS).astype(np.int64)
+    solid = (flags & lbm.FLAG_SOLID) > 0
+    phi = sim.read(lbm.FIELD_PHI)
+    p = sim.read(lbm.FIELD_P)
+    c = n / 2.0
+    R = wl.solids[0].radius
+    apex = measure.apex_height(phi, wl.shape, (n // 2, n // 2, 0), c + R, axis=2) - c
+    rho = wl.rho_g + (wl.rho_l - wl.rho_g) * phi
+    ph = rho * p
+    fluid = ~solid
+    o = sim.observe()
+    return {"theta_apex": measure.angle_from_apex(R, o["mass_blue"], apex, dim=3), "apex": apex,
+            "dp_h": float(ph[fluid & (phi > 0.999)].mean() - ph[fluid & (phi < 0.001)].mean()),
+            "max_speed": o["max_speed"], "mass_blue": o["mass_blue"]}
+
+
+def test_reduced_precision_contact_angle_against_oracle():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    gold = _golden()
+    if not gold:
+        pytest.skip("no oracle reference yet")
+    from paper_2605_30878_amd import lbm
+
+    thetas = sorted(float(t) for t in gold)
+    precs = [W.FP32, W.FP16_OFS, W.BF16_OFS]
+    cases = [(t, p) for t in thetas for p in precs]
+    steps = int(gold[str(thetas[0])]["steps"])
+    print(f"[angle] cases={cases} steps={steps}", flush=True)
+    wls = [W.sphere_d3q19(64, theta=t, precision=p, steps=steps) for t, p in cases]
+    sims = [lbm.Simulation(wl, W.initial_phi(wl)) for wl in wls]
+    batch = lbm.Batch(max_jobs=len(sims))
+    for _ in range(steps // 2000):
+        batch.step(sims, [2000] * len(sims))
+    batch.close()
+    worst = {}
+    for (t, p), wl, sim in zip(cases, wls, sims):
+        g = gold[str(t)]
+        m = _measure(lbm, sim, wl)
+        d_theta = m["theta_apex"] - g["theta_apex"]
+        r_speed = m["max_speed"] / g["max_speed"] - 1.0
+        r_dp = m["dp_h"] / g["dp_h"] - 1.0
+        r_mass = m["mass_blue"] / g["mass_blue"] - 1.0
+        name = W.PRECISION_NAMES[p]
+        print(f"[angle] theta={t} {name}: theta {m['theta_apex']:.3f} (oracle {g['theta_apex']:.3f}, "
+              f"diff {d_theta:+.3f}); max|u| {m['max_speed']:.3e} ({r_speed:+.2%}); "
+              f"dp_h {m['dp_h']:.4e} ({r_dp:+.2%}); mass {r_mass:+.2e}", flush=True)
+        worst[(t, name)] = (d_theta, r_speed, r_dp)
+        sim.close()
+    for (t, name), (d_theta, r_speed, r_dp) in worst.items():
+        assert abs(d_theta) <= 0.5, (t, name, d_theta)
+        assert abs(r_speed) <= 0.10, (t, name, r_speed)
+        assert abs(r_dp) <= 0.02, (t, name, r_dp)
