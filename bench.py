@@ -165,7 +165,8 @@ def main() -> int:
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": args.precision,
-        "data": "synthetic (analytic sphere and tanh drop, deterministic)",
+        "data": ("synthetic (analytic sphere and tanh drop, deterministic)" if args.workload == "sphere" else
+                 "synthetic (seeded random sphere packing, tanh liquid slab, deterministic)"),
         "config": ({"workload": f"D3Q19 drop on sphere {args.size}^3", "lattice": "D3Q19",
                     "box": [args.size] * 3, "sphere_radius": 48 * args.size / 256,
                     "drop_radius": 40 * args.size / 256, "rho_ratio": 1000, "mu_ratio": 100,

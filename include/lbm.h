@@ -79,8 +79,12 @@ enum {
     LBM_FIELD_U = 3,          /* [3][nodes] velocity u of Eq. A14 (read only) */
     LBM_FIELD_P = 4,          /* [nodes] auxiliary pressure p of Eq. A15 (read only) */
     LBM_FIELD_SOLID_PHI = 5,  /* [nodes] phi carried at solid nodes between steps */
-    LBM_FIELD_FLAGS = 6       /* [nodes] node class: 1 solid, 2 fluid next to a
+    LBM_FIELD_FLAGS = 6,      /* [nodes] node class: 1 solid, 2 fluid next to a
                                  solid, 4 ghost (read only) */
+    LBM_FIELD_N_OFFSET = 7    /* [Q][nodes] N_i - chi_i as the library stores it
+                                 (every precision keeps the offset from the
+                                 rest state); exact in FP64 both ways, so a
+                                 read-then-set checkpoint resumes bit for bit */
 };
 
 typedef struct lbm_ctx lbm_ctx;

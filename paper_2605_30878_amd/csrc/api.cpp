@@ -418,6 +418,11 @@ static int upload_aux(lbm_ctx* c, const double* src, int64_t count, int64_t plan
     return LBM_OK;
 }
 
+// Plane kind of the population fields for launch_plane_in / _out.
+static int n_plane_kind(int field) {
+    return field == LBM_FIELD_N ? 0 : field == LBM_FIELD_B ? 1 : 3;
+}
+
 int lbm_set_field(lbm_ctx* c, int field, const double* src, size_t count) {
     if (!c) return LBM_EINVAL;
     if (!c->wetting) return fail(c, LBM_ESTATE, "set geometry, bind and wetting first");
@@ -441,6 +446,7 @@ int lbm_set_field(lbm_ctx* c, int field, const double* src, size_t count) {
         c->started = true;
         return LBM_OK;
     case LBM_FIELD_N:
+    case LBM_FIELD_N_OFFSET:
     case LBM_FIELD_B:
         if (!c->started) return fail(c, LBM_ESTATE, "set PHI first");
         if (count != (size_t)c->Q * n) return fail(c, LBM_EINVAL, "N/B need Q*n values");
@@ -455,7 +461,7 @@ int lbm_set_field(lbm_ctx* c, int field, const double* src, size_t count) {
         }
         for (int i = 0; i < c->Q; i++) {
             if ((rc = upload_aux(c, src + (size_t)i * n, n, 0)) != LBM_OK) return rc;
-            HIPCHK(c, launch_plane_in(lat, prec, c->d, c->sp, field == LBM_FIELD_N ? 0 : 1, i, c->cur, c->stream),
+            HIPCHK(c, launch_plane_in(lat, prec, c->d, c->sp, n_plane_kind(field), i, c->cur, c->stream),
                    "plane in");
         }
         HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
@@ -611,10 +617,11 @@ int lbm_read_field(lbm_ctx* c, int field, double* dst, size_t count) {
             if ((rc = download(c, dst + (size_t)a * n, c->d.aux + (size_t)a * c->S, n)) != LBM_OK) return rc;
         return LBM_OK;
     case LBM_FIELD_N:
+    case LBM_FIELD_N_OFFSET:
     case LBM_FIELD_B:
         if (count != (size_t)c->Q * n) return fail(c, LBM_EINVAL, "N/B have Q*n values");
         for (int i = 0; i < c->Q; i++) {
-            HIPCHK(c, launch_plane_out(lat, prec, c->d, c->sp, field == LBM_FIELD_N ? 0 : 1, i, c->cur, c->ps,
+            HIPCHK(c, launch_plane_out(lat, prec, c->d, c->sp, n_plane_kind(field), i, c->cur, c->ps,
                                        c->from_planes, c->stream),
                    "plane out");
             if ((rc = download(c, dst + (size_t)i * n, c->d.aux, n)) != LBM_OK) return rc;

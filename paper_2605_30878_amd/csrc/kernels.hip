@@ -60,27 +60,30 @@ __device__ __forceinline__ T cmul(T v) {
     else return T(0);
 }
 
-// Storage of the colour-blind populations.  FP64 / FP32 runs store the
-// value itself.  16-bit runs store the offset from the rest state,
-// h_i = (N_i - chi_i) / s with a power-of-two scale s (FP16 or BF16, rounded
-// to nearest even), so N_i = chi_i + s h_i; arithmetic stays FP32.
-// The rest population closes the zeroth moment of the stored values:
-// sum_i N*_i = 1 exactly in the model (Eq. A4 sums to 1 and the forcing has no
-// zeroth moment), so N*_0 is written as the closure of the other Q - 1
-// stored values ("off" space: the value itself, or the 16-bit offset).
+// Storage of the colour-blind populations as offsets from the rest state,
+// n_i = N_i - chi_i (every precision).  Near rest the populations differ
+// from chi_i by ~1e-6 .. 1e-2, so moments, the equilibrium and the closure
+// below work on small numbers: the pressure p (a difference of O(1) sums
+// when N_i is carried whole) keeps its relative precision in FP32.  FP64 /
+// FP32 runs store n_i itself; 16-bit runs store h_i = n_i / s with a
+// power-of-two scale s (FP16 or BF16, rounded to nearest even); arithmetic
+// stays FP32.  The rest population closes the zeroth moment of the stored
+// values: sum_i N*_i = 1 exactly in the model (Eq. A4 sums to 1 and the
+// forcing has no zeroth moment), so n*_0 is written as the closure of the
+// other Q - 1 stored values ("off" space: the offset, or the 16-bit code).
 template <class T, class SN>
 struct NStore {
-    static constexpr bool offset = false;
-    __device__ __forceinline__ static T dec(SN h, T, T) { return h; }
-    __device__ __forceinline__ static SN enc(T v, T, T) { return v; }
+    static constexpr bool scaled = false;
+    __device__ __forceinline__ static T dec(SN h, T) { return h; }
+    __device__ __forceinline__ static SN enc(T v, T) { return v; }
     __device__ __forceinline__ static T off(SN h) { return h; }
     __device__ __forceinline__ static SN enc_off(T o) { return o; }
 };
 template <class SN>
 struct NStore16 {
-    static constexpr bool offset = true;
-    __device__ __forceinline__ static float dec(SN h, float chi, float s) { return chi + s * (float)h; }
-    __device__ __forceinline__ static SN enc(float v, float chi, float inv_s) { return (SN)((v - chi) * inv_s); }
+    static constexpr bool scaled = true;
+    __device__ __forceinline__ static float dec(SN h, float s) { return s * (float)h; }
+    __device__ __forceinline__ static SN enc(float v, float inv_s) { return (SN)(v * inv_s); }
     __device__ __forceinline__ static float off(SN h) { return (float)h; }
     __device__ __forceinline__ static SN enc_off(float o) { return (SN)o; }
 };
@@ -97,10 +100,9 @@ struct KParams {
     T sigma, W, inv_W;
     T g[3];
     T chi[Q];
-    T chi0;
     T n_thresh2;            // |grad phi|^2 below which n_phi = 0
     T n_s, n_inv_s;         // 16-bit storage scale of N and its inverse
-    T n_close;              // target of the closure sum in "off" space
+    T n_close;              // target of the closure sum in "off" space: (1 - sum chi) / s
     int nx, ny, nz;
     int64_t S;
 };
@@ -121,20 +123,14 @@ static KParams<T, L::Q> make_kparams(const StepParams& p) {
     k.inv_W = T(1.0 / p.W);
     for (int a = 0; a < 3; a++) k.g[a] = T(L::D == 2 && a == 2 ? 0.0 : p.g[a]);
     for (int i = 0; i < L::Q; i++) k.chi[i] = T(p.chi[i]);
-    k.chi0 = T(p.chi0);
     // |grad phi| > 1e-12 (FP64) or > 1e-7 (FP32) defines the interface normal
     k.n_thresh2 = std::is_same<T, double>::value ? T(1e-24) : T(1e-14);
-    if (NStore<T, SN>::offset) {
-        double sum_chi = 0.0;
-        for (int i = 0; i < L::Q; i++) sum_chi += (double)k.chi[i];
-        k.n_s = T(N16_SCALE);
-        k.n_inv_s = T(1.0 / N16_SCALE);
-        k.n_close = T((1.0 - sum_chi) / N16_SCALE);
-    } else {
-        k.n_s = T(1);
-        k.n_inv_s = T(1);
-        k.n_close = T(1);
-    }
+    const double scale = NStore<T, SN>::scaled ? N16_SCALE : 1.0;
+    double sum_chi = 0.0;
+    for (int i = 0; i < L::Q; i++) sum_chi += (double)k.chi[i];
+    k.n_s = T(scale);
+    k.n_inv_s = T(1.0 / scale);
+    k.n_close = T((1.0 - sum_chi) / scale);
     k.nx = p.nx;
     k.ny = p.ny;
     k.nz = p.nz;
@@ -158,7 +154,8 @@ struct Macro {
     T a[3];  // F / rho
 };
 
-// Macroscopic stage of one fluid node: colour stencils, mixture properties,
+// Macroscopic stage of one fluid node (N holds offsets n_i = N_i - chi_i):
+// colour stencils, mixture properties,
 // u0 and p (Eq. A14-A15 with the unforced velocity), forces (Eq. 4, Eq. 2,
 // Eq. A9-A11), forced velocity u = u0 + F/(2 rho).  Also returns the raw
 // second moments Pi_ab = sum_i c_ia c_ib N_i for the collision.
@@ -211,9 +208,12 @@ __device__ __forceinline__ void macro_stage(const T (&N)[L::Q], const T (&ph)[L:
         if constexpr (cx * cz != 0) pxz += cmul<cx * cz>(n);
     });
     Pi[0] = pxx; Pi[1] = pyy; Pi[2] = pzz; Pi[3] = pxy; Pi[4] = pyz; Pi[5] = pxz;
-    // Eq. A15 with u0 = sum c N (the forced u needs F_p(p)).
+    // Eq. A15 with u0 = sum c N (the forced u needs F_p(p)); s = sum_{i>0} n_i
+    // already excludes sum_{i>0} chi_i = 1 - chi_0, and chi has no first
+    // moment.  The chi part of Pi is isotropic (chi2 I) and drops out of every
+    // use below (deviators and differences of diagonal entries).
     const T uu0 = jx * jx + jy * jy + jz * jz;
-    const T p = ((s - (T(1) - P.chi0)) * T(1.0 / 3.0) - T(0.5) * w0 * uu0) / (T(1) - w0);
+    const T p = (s * T(1.0 / 3.0) - T(0.5) * w0 * uu0) / (T(1) - w0);
     m.p = p;
     // Surface tension (Eq. 4): F_s = mu grad phi.
     const T mu = -P.sigma * (T(48) * P.inv_W * phi * (T(1) - phi) * (phi - T(0.5)) + T(1.5) * P.W * lap);
@@ -249,7 +249,8 @@ __device__ __forceinline__ void macro_stage(const T (&N)[L::Q], const T (&ph)[L:
 
 // Collision in projection form, exactly equal to Eq. A1 with S relaxing the
 // traceless second moments at 1/tau and every other moment at 1:
-//   N* = N^eq(u, p) + F/2 + (1 - 1/tau) P_sigma (N - N^eq(u, p)).
+//   N* = N^eq(u, p) + F/2 + (1 - 1/tau) P_sigma (N - N^eq(u, p)),
+// returned as offsets Ns_i = N*_i - chi_i.
 // Also returns the recolouring vector G = (2/W) max(phi(1 - phi), 0) n_phi
 // of Eq. A12.
 template <class L, class T>
@@ -275,15 +276,15 @@ __device__ __forceinline__ void collide_stage(const Macro<T>& m, const T (&Pi)[6
         s4 = omega * (Pi[4] - uy * uz) * T(0.25);
         s5 = omega * (Pi[5] - ux * uz) * T(0.25);
     }
-    // The rest direction has no stress moment.
-    Ns[0] = P.chi[0] - (T(1) - w0) * p3 - w0 * T(1.5) * uu;
+    // Offsets n*_i = N*_i - chi_i.  The rest direction has no stress moment.
+    Ns[0] = -(T(1) - w0) * p3 - w0 * T(1.5) * uu;
     static_for<1, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
         constexpr T wi = T(L::w[i]);
         const T cu = cmul<cx>(ux) + cmul<cy>(uy) + cmul<cz>(uz);
         const T ca = cmul<cx>(m.a[0]) + cmul<cy>(m.a[1]) + cmul<cz>(m.a[2]);
-        const T neq = P.chi[i] + wi * (p3 + T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu);
+        const T neq = wi * (p3 + T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu);
         // projection onto the stress rows, m_k(i) evaluated at compile time
         T proj;
         if constexpr (L::D == 2) {
@@ -345,9 +346,43 @@ __device__ __forceinline__ bool row_index(int nx, int ny, RowIdx& r) {
     return true;
 }
 
+// Row schedule of the two hot stencil kernels over a 1-D grid of
+// xb * ny * nz row blocks.  Consecutive workgroups are dispatched round-robin
+// to the 8 XCDs, each with its own L2.  With band > 0 (ny = 8 band) XCD k
+// takes rows y in [k band, (k + 1) band) of every plane, plane after plane, so
+// the y +- 1 and z +- 1 neighbour rows a stencil reads are mostly in its own
+// L2 (the row-major order spreads y-neighbours over three XCDs, each fetching
+// the row again).  Any order computes the same result.
+struct RowSched {
+    int xb, ny, band;
+};
+
+__device__ __forceinline__ bool row_index_sched(const RowSched& s, int nx, RowIdx& r) {
+    const int64_t L = blockIdx.x;
+    int64_t bxi, y, z;
+    if (s.band > 0) {
+        const int64_t j = L >> 3;
+        bxi = j % s.xb;
+        const int64_t t = j / s.xb;
+        y = (L & 7) * (int64_t)s.band + t % s.band;
+        z = t / s.band;
+    } else {
+        bxi = L % s.xb;
+        const int64_t t = L / s.xb;
+        y = t % s.ny;
+        z = t / s.ny;
+    }
+    r.ix = (int)bxi * blockDim.x + threadIdx.x;
+    if (r.ix >= nx) return false;
+    r.iy = (int)y;
+    r.iz = (int)z;
+    r.x = (int64_t)r.ix + (int64_t)nx * (y + (int64_t)s.ny * z);
+    return true;
+}
+
 // One term of the compact liquid population: phi(src) N_i(y) +
-// sgn (c_i . G(src)) (chi_i + w_i p(src) / cs^2); components of G along
-// zero components of c_i are not used.
+// sgn (c_i . G(src)) (chi_i + w_i p(src) / cs^2) with N_i = chi_i + n;
+// components of G along zero components of c_i are not used.
 template <class L, class T, int I>
 __device__ __forceinline__ T compact_term(T n, T phi_src, T gx, T gy, T gz, T p, T sgn,
                                           const KParams<T, L::Q>& P) {
@@ -357,7 +392,8 @@ __device__ __forceinline__ T compact_term(T n, T phi_src, T gx, T gy, T gz, T p,
     if constexpr (cx != 0) cG += cmul<cx>(gx);
     if constexpr (cy != 0) cG += cmul<cy>(gy);
     if constexpr (cz != 0) cG += cmul<cz>(gz);
-    return phi_src * n + sgn * cG * (P.chi[I] + wi * T(3) * p);
+    const T sG = sgn * cG;
+    return (phi_src + sG) * P.chi[I] + phi_src * n + sG * (wi * T(3) * p);
 }
 
 // Post-stream liquid population B_i(y) from the compact record.  nb[i] is
@@ -369,9 +405,9 @@ __device__ __forceinline__ T compact_B(const SN* __restrict__ N, const T* __rest
                                        const KParams<T, L::Q>& P, int64_t y, const int64_t (&nb)[L::Q],
                                        bool near_solid) {
     const int64_t S = P.S;
-    const T n = NStore<T, SN>::dec(N[(int64_t)I * S + y], P.chi[I], P.n_s);
+    const T n = NStore<T, SN>::dec(N[(int64_t)I * S + y], P.n_s);
     if constexpr (I == 0) {
-        return phi_prev[y] * n;
+        return phi_prev[y] * (P.chi[0] + n);
     } else {
         constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
         int64_t src = nb[L::opp[I]];
@@ -431,10 +467,128 @@ __device__ __forceinline__ void colour_compact_node(const SN* __restrict__ N, co
 template <class L, class T, class SN>
 __global__ __launch_bounds__(256) void k_colour_compact(const SN* __restrict__ N, const T* __restrict__ phi_prev,
                                                         const T* __restrict__ G, const uint8_t* __restrict__ flags,
-                                                        T* __restrict__ phi, KParams<T, L::Q> P) {
+                                                        T* __restrict__ phi, KParams<T, L::Q> P, RowSched rs) {
     RowIdx r;
-    if (!row_index(P.nx, P.ny, r)) return;
+    if (!row_index_sched(rs, P.nx, r)) return;
     colour_compact_node<L, T, SN>(N, phi_prev, G, flags, phi, P, r.ix, r.iy, r.iz);
+}
+
+// Colour field of D3Q19 boxes in z-marching tiles: a workgroup owns a
+// CTX x CTY column of nodes and walks up a chunk of planes, keeping the
+// compact record (phi_prev, G, p) and flags of three planes of the tile and
+// a one-node ring in LDS.  Every record is fetched from memory once per
+// workgroup (plus the ring and two prologue planes) instead of once per
+// reading node (18 neighbours, 3 to 4 values each); N is read straight into
+// registers before the plane's barrier.  Per node the arithmetic is the row
+// kernel's: the same compact_term in the same order.
+constexpr int CTX = 64, CTY = 4;                  // tile
+constexpr int CRX = CTX + 2, CRY = CTY + 2;       // tile + ring
+
+template <class T>
+struct ColourSmem {
+    T rec[3][5][CRY][CRX];     // phi_prev, Gx, Gy, Gz, p; planes by slot3(z)
+    uint8_t fl[3][CRY][CRX];
+};
+
+__device__ __forceinline__ int wrapc(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+__device__ __forceinline__ int slot3(int z) { return (z % 3 + 3) % 3; }
+
+// Tile schedule over a 1-D grid: XCD k (blocks with id % 8 == k) takes the
+// y-band [k yb, (k + 1) yb) of tiles when band > 0, x-tiles fastest, then
+// y-tiles of the band, then z-chunks.
+struct TileSched {
+    int xt, yt, band;  // tiles in x and y; y-tiles per XCD (0: plain order)
+};
+
+__device__ __forceinline__ void tile_index(const TileSched& s, int& bx, int& by, int& bz) {
+    const int L = blockIdx.x;
+    if (s.band > 0) {
+        const int j = L >> 3;
+        bx = j % s.xt;
+        const int t = j / s.xt;
+        by = (L & 7) * s.band + t % s.band;
+        bz = t / s.band;
+    } else {
+        bx = L % s.xt;
+        const int t = L / s.xt;
+        by = t % s.yt;
+        bz = t / s.yt;
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void colour_tile_load(ColourSmem<T>& sm, int z, int x0, int y0,
+                                                 const T* __restrict__ phi_prev, const T* __restrict__ G,
+                                                 const uint8_t* __restrict__ flags, int nx, int ny, int nz,
+                                                 int64_t S) {
+    const int sl = slot3(z);
+    const int Z = wrapc(z, nz);
+    for (int k = threadIdx.x; k < CRX * CRY; k += CTX * CTY) {
+        const int lx = k % CRX, ly = k / CRX;
+        const int X = wrapc(x0 + lx - 1, nx), Y = wrapc(y0 + ly - 1, ny);
+        const int64_t id = (int64_t)X + (int64_t)nx * ((int64_t)Y + (int64_t)ny * Z);
+        sm.rec[sl][0][ly][lx] = phi_prev[id];
+        sm.rec[sl][1][ly][lx] = G[id];
+        sm.rec[sl][2][ly][lx] = G[S + id];
+        sm.rec[sl][3][ly][lx] = G[2 * S + id];
+        sm.rec[sl][4][ly][lx] = G[3 * S + id];
+        sm.fl[sl][ly][lx] = flags[id];
+    }
+}
+
+template <class T, class SN>
+__global__ __launch_bounds__(CTX * CTY) void k_colour_tile(const SN* __restrict__ N, const T* __restrict__ phi_prev,
+                                                           const T* __restrict__ G, const uint8_t* __restrict__ flags,
+                                                           T* __restrict__ phi, KParams<T, 19> P, TileSched ts,
+                                                           int zc) {
+    using L = LatD3Q19;
+    __shared__ ColourSmem<T> sm;
+    int bx, by, bz;
+    tile_index(ts, bx, by, bz);
+    const int x0 = bx * CTX, y0 = by * CTY;
+    const int z0 = bz * zc;
+    const int z1 = min(z0 + zc, P.nz);
+    const int tx = threadIdx.x % CTX, ty = threadIdx.x / CTX;
+    const int64_t S = P.S;
+    colour_tile_load<T>(sm, z0 - 1, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
+    colour_tile_load<T>(sm, z0, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
+    for (int z = z0; z < z1; z++) {
+        const int64_t x = (int64_t)(x0 + tx) + (int64_t)P.nx * ((int64_t)(y0 + ty) + (int64_t)P.ny * z);
+        SN raw[19];
+#pragma unroll
+        for (int i = 0; i < 19; i++) raw[i] = N[(int64_t)i * S + x];
+        colour_tile_load<T>(sm, z + 1, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
+        __syncthreads();
+        const int s0 = slot3(z), sx = tx + 1, sy = ty + 1;
+        const uint8_t f = sm.fl[s0][sy][sx];
+        if (!(f & FLAG_SOLID)) {
+            const bool near = (f & FLAG_NEAR_SOLID) != 0;
+            T acc = 0;
+            static_for<0, L::Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+                const T n = NStore<T, SN>::dec(raw[i], P.n_s);
+                if constexpr (i == 0) {
+                    acc += sm.rec[s0][0][sy][sx] * (P.chi[0] + n);
+                } else {
+                    int sl = slot3(z - cz), qx = sx - cx, qy = sy - cy;
+                    T sgn = T(1);
+                    if (near && (sm.fl[sl][qy][qx] & FLAG_SOLID)) {
+                        sl = s0;
+                        qx = sx;
+                        qy = sy;
+                        sgn = T(-1);
+                    }
+                    const T gx = cx != 0 ? sm.rec[sl][1][qy][qx] : T(0);
+                    const T gy = cy != 0 ? sm.rec[sl][2][qy][qx] : T(0);
+                    const T gz = cz != 0 ? sm.rec[sl][3][qy][qx] : T(0);
+                    acc += compact_term<L, T, i>(n, sm.rec[sl][0][qy][qx], gx, gy, gz, sm.rec[sl][4][qy][qx], sgn, P);
+                }
+            });
+            phi[x] = acc;
+        }
+        __syncthreads();
+    }
 }
 
 // One direction plane of B from the compact record into FP64 (read-out).
@@ -514,7 +668,7 @@ __device__ __forceinline__ void collide_node(const SN* __restrict__ Nsrc, SN* __
     using NS = NStore<T, SN>;
     T N[Q], ph[Q];
 #pragma unroll
-    for (int i = 0; i < Q; i++) N[i] = NS::dec(Nsrc[(int64_t)i * P.S + x], P.chi[i], P.n_s);
+    for (int i = 0; i < Q; i++) N[i] = NS::dec(Nsrc[(int64_t)i * P.S + x], P.n_s);
 #pragma unroll
     for (int i = 0; i < Q; i++) ph[i] = phi[nb[i]];
     Macro<T> m;
@@ -527,7 +681,7 @@ __device__ __forceinline__ void collide_node(const SN* __restrict__ Nsrc, SN* __
     T closure = P.n_close;
 #pragma unroll
     for (int i = 1; i < Q; i++) {
-        e[i] = NS::enc(Ns[i], P.chi[i], P.n_inv_s);
+        e[i] = NS::enc(Ns[i], P.n_inv_s);
         closure -= NS::off(e[i]);
     }
     e[0] = NS::enc_off(closure);
@@ -552,9 +706,9 @@ template <class L, class T, class SN>
 __global__ __launch_bounds__(LBM_COLLIDE_BX) void k_collide_stream(const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
                                                                    T* __restrict__ Gdst, const T* __restrict__ phi,
                                                                    const uint8_t* __restrict__ flags,
-                                                                   KParams<T, L::Q> P) {
+                                                                   KParams<T, L::Q> P, RowSched rs) {
     RowIdx r;
-    if (!row_index(P.nx, P.ny, r)) return;
+    if (!row_index_sched(rs, P.nx, r)) return;
     collide_node<L, T, SN>(Nsrc, Ndst, Gdst, phi, flags, P, r.ix, r.iy, r.iz);
 }
 
@@ -579,7 +733,7 @@ __global__ __launch_bounds__(256) void k_macro(const SN* __restrict__ Nsrc, cons
     neighbours<L>(r.ix, r.iy, r.iz, P.nx, P.ny, P.nz, nb);
     T N[Q], ph[Q];
 #pragma unroll
-    for (int i = 0; i < Q; i++) N[i] = NStore<T, SN>::dec(Nsrc[(int64_t)i * S + x], P.chi[i], P.n_s);
+    for (int i = 0; i < Q; i++) N[i] = NStore<T, SN>::dec(Nsrc[(int64_t)i * S + x], P.n_s);
 #pragma unroll
     for (int i = 0; i < Q; i++) ph[i] = phi[nb[i]];
     Macro<T> m;
@@ -702,7 +856,7 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ phi0, c
         phiB[x] = phi_solid;
 #pragma unroll
         for (int i = 0; i < L::Q; i++) {
-            N[(int64_t)i * S + x] = NStore<T, SN>::enc(P.chi[i], P.chi[i], P.n_inv_s);
+            N[(int64_t)i * S + x] = NStore<T, SN>::enc(T(0), P.n_inv_s);
             B[(int64_t)i * S + x] = T(0);
         }
         return;
@@ -712,7 +866,7 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ phi0, c
     phiB[x] = ph;
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
-        N[(int64_t)i * S + x] = NStore<T, SN>::enc(P.chi[i], P.chi[i], P.n_inv_s);
+        N[(int64_t)i * S + x] = NStore<T, SN>::enc(T(0), P.n_inv_s);
         B[(int64_t)i * S + x] = ph * P.chi[i];
     }
 }
@@ -742,7 +896,7 @@ __global__ __launch_bounds__(256) void k_nplane_out(const SN* __restrict__ src, 
                                                     T chi, T s, double* __restrict__ dst, int64_t n) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
-    dst[x] = (flags[x] & FLAG_SOLID) ? 0.0 : (double)NStore<T, SN>::dec(src[x], chi, s);
+    dst[x] = (flags[x] & FLAG_SOLID) ? 0.0 : (double)chi + (double)NStore<T, SN>::dec(src[x], s);
 }
 
 template <class T, class SN>
@@ -750,7 +904,7 @@ __global__ __launch_bounds__(256) void k_nplane_in(const double* __restrict__ sr
                                                    T inv_s, int64_t n) {
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
-    dst[x] = NStore<T, SN>::enc((T)src[x], chi, inv_s);
+    dst[x] = NStore<T, SN>::enc((T)(src[x] - (double)chi), inv_s);
 }
 
 template <class T>
@@ -786,9 +940,6 @@ constexpr int FTX = 32, FTY = 8;                 // tile
 constexpr int FRX = FTX + 2, FRY = FTY + 2;      // tile + 1 ring (phi window)
 constexpr int FSX = FTX + 4, FSY = FTY + 4;      // tile + 2 rings (record window)
 constexpr int FKS = 5;                           // phi_prev, Gx, Gy, Gz, p
-
-__device__ __forceinline__ int wrapc(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
-__device__ __forceinline__ int slot3(int z) { return (z % 3 + 3) % 3; }
 
 // Ghost pre-pass of the fused step: like k_ghost, but the fluid corners'
 // phi^{n+1} are formed here from the compact record (the colour field of
@@ -878,9 +1029,9 @@ __device__ __forceinline__ T fused_phi_node(const FusedSmem<T, SN>& sm, int z, i
     static_for<0, L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-        n[i] = NStore<T, SN>::dec(N[(int64_t)i * P.S + id], P.chi[i], P.n_s);
+        n[i] = NStore<T, SN>::dec(N[(int64_t)i * P.S + id], P.n_s);
         if constexpr (i == 0) {
-            acc += sm.rec[slot3(z)][0][sy][sx] * n[0];
+            acc += sm.rec[slot3(z)][0][sy][sx] * (P.chi[0] + n[0]);
         } else {
             int s = slot3(z - cz), qx = sx - cx, qy = sy - cy;
             T sgn = T(1);
@@ -982,7 +1133,7 @@ __global__ __launch_bounds__(FTX * FTY) void k_step_fused(const SN* __restrict__
             T closure = P.n_close;
 #pragma unroll
             for (int i = 1; i < Q; i++) {
-                e[i] = NS::enc(Ns[i], P.chi[i], P.n_inv_s);
+                e[i] = NS::enc(Ns[i], P.n_inv_s);
                 closure -= NS::off(e[i]);
             }
             e[0] = NS::enc_off(closure);
@@ -1101,9 +1252,55 @@ static inline dim3 row_grid(const StepParams& p, int bx) {
     return dim3((unsigned)((p.nx + bx - 1) / bx), (unsigned)p.ny, (unsigned)p.nz);
 }
 
+// Row block: the widest of 256 / 192 / 128 / 64 threads that divides nx
+// (no idle lanes), else 256 / 128 / 64 by size.
 static inline int row_block(int nx) {
+    for (int b : {256, 192, 128, 64})
+        if (b <= LBM_COLLIDE_BX && nx % b == 0) return b;
     int b = nx >= 256 ? 256 : (nx >= 128 ? 128 : 64);
     return b > LBM_COLLIDE_BX ? LBM_COLLIDE_BX : b;
+}
+
+#ifndef LBM_XCD_BANDS
+#define LBM_XCD_BANDS 1
+#endif
+
+static inline RowSched row_sched(const StepParams& p, int bx) {
+    RowSched s;
+    s.xb = (p.nx + bx - 1) / bx;
+    s.ny = p.ny;
+    s.band = (LBM_XCD_BANDS && p.ny % 8 == 0) ? p.ny / 8 : 0;
+    return s;
+}
+
+static inline dim3 row_grid1(const RowSched& s, const StepParams& p) {
+    return dim3((unsigned)((int64_t)s.xb * p.ny * p.nz));
+}
+
+#ifndef LBM_COLOUR_TILE
+#define LBM_COLOUR_TILE 1
+#endif
+
+// The z-marching colour kernel takes D3Q19 boxes tiled exactly by CTX x CTY.
+static inline bool colour_tile_ok(const StepParams& p) {
+    return LBM_COLOUR_TILE && p.nz > 1 && p.nx % CTX == 0 && p.ny % CTY == 0;
+}
+
+// z-chunk: about 2048 workgroups, at least 4 planes each.
+static inline int colour_tile_chunk(const StepParams& p) {
+    const int64_t cols = (int64_t)(p.nx / CTX) * (p.ny / CTY);
+    int64_t zc = (p.nz * cols + 2047) / 2048;
+    if (zc < 4) zc = 4;
+    if (zc > p.nz) zc = p.nz;
+    return (int)zc;
+}
+
+static inline TileSched tile_sched(const StepParams& p) {
+    TileSched s;
+    s.xt = p.nx / CTX;
+    s.yt = p.ny / CTY;
+    s.band = (LBM_XCD_BANDS && s.yt % 8 == 0) ? s.yt / 8 : 0;
+    return s;
 }
 
 // The fused one-launch step applies to D3Q19 boxes tiled exactly by 32 x 8
@@ -1160,8 +1357,20 @@ static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int
                                (const T*)d.B, work, d.flags, p.n, p.S);
         } else {
             const KParams<T, L::Q> kp = make_kparams<T, L, SN>(p);
-            hipLaunchKernelGGL((k_colour_compact<L, T, SN>), row_grid(p, bx), dim3(bx), 0, st, (const SN*)d.N[cur],
-                               (const T*)d.phi[ps], (const T*)d.G[cur], d.flags, work, kp);
+            if constexpr (L::D == 3) {
+                if (colour_tile_ok(p)) {
+                    const int zc = colour_tile_chunk(p);
+                    const TileSched ts = tile_sched(p);
+                    const unsigned nb = (unsigned)(ts.xt * ts.yt * ((p.nz + zc - 1) / zc));
+                    hipLaunchKernelGGL((k_colour_tile<T, SN>), dim3(nb), dim3(CTX * CTY), 0, st,
+                                       (const SN*)d.N[cur], (const T*)d.phi[ps], (const T*)d.G[cur], d.flags, work,
+                                       kp, ts, zc);
+                    return hipGetLastError();
+                }
+            }
+            const RowSched rs = row_sched(p, bx);
+            hipLaunchKernelGGL((k_colour_compact<L, T, SN>), row_grid1(rs, p), dim3(bx), 0, st,
+                               (const SN*)d.N[cur], (const T*)d.phi[ps], (const T*)d.G[cur], d.flags, work, kp, rs);
         }
     } else if (phase == 1) {
         if (d.n_ghost > 0) {
@@ -1171,8 +1380,9 @@ static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int
         }
     } else {
         const KParams<T, L::Q> kp = make_kparams<T, L, SN>(p);
-        hipLaunchKernelGGL((k_collide_stream<L, T, SN>), row_grid(p, bx), dim3(bx), 0, st, (const SN*)d.N[cur],
-                           (SN*)d.N[1 - cur], (T*)d.G[1 - cur], (const T*)work, d.flags, kp);
+        const RowSched rs = row_sched(p, bx);
+        hipLaunchKernelGGL((k_collide_stream<L, T, SN>), row_grid1(rs, p), dim3(bx), 0, st, (const SN*)d.N[cur],
+                           (SN*)d.N[1 - cur], (T*)d.G[1 - cur], (const T*)work, d.flags, kp, rs);
     }
     return hipGetLastError();
 }
@@ -1226,7 +1436,8 @@ static hipError_t init_t(const DevState& d, const StepParams& p, int cur, int ps
 }
 
 // which: 0 = N plane `dir` of buffer cur, 1 = B plane `dir` (planes buffer
-// when from_planes, else formed from the compact record), 2 = phi buffer `dir`.
+// when from_planes, else formed from the compact record), 2 = phi buffer `dir`,
+// 3 = N plane `dir` as the stored offset N_i - chi_i (exact in FP64).
 template <class L, class T, class SN>
 static hipError_t plane_out_t(const DevState& d, const StepParams& p, int which, int dir, int cur, int ps,
                               int from_planes, hipStream_t st) {
@@ -1237,10 +1448,10 @@ static hipError_t plane_out_t(const DevState& d, const StepParams& p, int which,
                            (const T*)d.phi[ps], (const T*)d.G[cur], d.flags, kp, dir, d.aux);
         return hipGetLastError();
     }
-    if (which == 0) {
+    if (which == 0 || which == 3) {
         hipLaunchKernelGGL((k_nplane_out<T, SN>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st,
-                           (const SN*)d.N[cur] + (int64_t)dir * p.S, d.flags, (T)p.chi[dir],
-                           (T)(NStore<T, SN>::offset ? N16_SCALE : 1.0), d.aux, p.n);
+                           (const SN*)d.N[cur] + (int64_t)dir * p.S, d.flags, which == 0 ? (T)p.chi[dir] : T(0),
+                           (T)(NStore<T, SN>::scaled ? N16_SCALE : 1.0), d.aux, p.n);
         return hipGetLastError();
     }
     const T* src = which == 1 ? (const T*)d.B + (int64_t)dir * p.S : (const T*)d.phi[dir];
@@ -1250,7 +1461,7 @@ static hipError_t plane_out_t(const DevState& d, const StepParams& p, int which,
 }
 
 // which: 0 = N plane `dir` of buffer cur, 1 = B plane `dir` (planes buffer),
-// 2 = solid entries of both phi buffers.
+// 2 = solid entries of both phi buffers, 3 = N plane `dir` from offsets.
 template <class L, class T, class SN>
 static hipError_t plane_in_t(const DevState& d, const StepParams& p, int which, int dir, int cur, hipStream_t st) {
     if (which == 2) {
@@ -1258,10 +1469,10 @@ static hipError_t plane_in_t(const DevState& d, const StepParams& p, int which, 
                            (T*)d.phi[0], (T*)d.phi[1], p.n);
         return hipGetLastError();
     }
-    if (which == 0) {
+    if (which == 0 || which == 3) {
         hipLaunchKernelGGL((k_nplane_in<T, SN>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st, d.aux,
-                           (SN*)d.N[cur] + (int64_t)dir * p.S, (T)p.chi[dir],
-                           (T)(NStore<T, SN>::offset ? 1.0 / N16_SCALE : 1.0), p.n);
+                           (SN*)d.N[cur] + (int64_t)dir * p.S, which == 0 ? (T)p.chi[dir] : T(0),
+                           (T)(NStore<T, SN>::scaled ? 1.0 / N16_SCALE : 1.0), p.n);
         return hipGetLastError();
     }
     T* dst = (T*)d.B + (int64_t)dir * p.S;

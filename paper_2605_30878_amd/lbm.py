@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 ABI_VERSION = 1
 OK, EINVAL, ESTATE, ENOMEM, EHIP, EUNSTABLE = 0, -1, -2, -3, -4, -5
 OPT_FUSED = 1
-FIELD_PHI, FIELD_N, FIELD_B, FIELD_U, FIELD_P, FIELD_SOLID_PHI, FIELD_FLAGS = range(7)
+FIELD_PHI, FIELD_N, FIELD_B, FIELD_U, FIELD_P, FIELD_SOLID_PHI, FIELD_FLAGS, FIELD_N_OFFSET = range(8)
 FLAG_SOLID, FLAG_NEAR_SOLID, FLAG_GHOST = 1, 2, 4
 
 EXPORTED = ["lbm_create", "lbm_set_geometry", "lbm_device_bytes", "lbm_bind", "lbm_set_wetting",
@@ -65,6 +65,9 @@ def load_library(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"{path} is missing: build it with `python -m paper_2605_30878_amd.build_lib`")
+    # torch first: its HIP runtime is then the one the library binds to, so
+    # device pointers from torch's allocator are known to the library's calls
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     vp, dp = C.c_void_p, C.POINTER(C.c_double)
     lib.lbm_create.argtypes = [C.POINTER(lbm_params), C.POINTER(vp)]
@@ -202,10 +205,11 @@ class Simulation:
         return {"colour": ms[0], "ghost": ms[1], "collide": ms[2], "total": ms[3]}
 
     def read(self, field: int) -> np.ndarray:
-        size = {FIELD_N: self.Q * self.n, FIELD_B: self.Q * self.n, FIELD_U: 3 * self.n}.get(field, self.n)
+        size = {FIELD_N: self.Q * self.n, FIELD_N_OFFSET: self.Q * self.n, FIELD_B: self.Q * self.n,
+                FIELD_U: 3 * self.n}.get(field, self.n)
         out = np.zeros(size, dtype=np.float64)
         self._check(self.lib.lbm_read_field(self._h, int(field), _dp(out), size))
-        if field in (FIELD_N, FIELD_B):
+        if field in (FIELD_N, FIELD_N_OFFSET, FIELD_B):
             return out.reshape(self.Q, self.n)
         if field == FIELD_U:
             return out.reshape(3, self.n)

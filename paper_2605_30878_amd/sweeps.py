@@ -133,14 +133,21 @@ def main():
     ap.add_argument("--which", choices=["cylinder", "plate", "both"], default="both")
     ap.add_argument("--steps", type=int, default=40000)
     ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
-    ap.add_argument("--W", type=float, default=4.0)
+    ap.add_argument("--W", type=float, nargs="+", default=[4.0],
+                    help="interface widths of the plate sweep (one batch per width)")
+    ap.add_argument("--thetas", type=float, nargs="+", default=[30.0, 60.0, 90.0, 120.0, 150.0])
     args = ap.parse_args()
     prec = W.FP64 if args.precision == "f64" else W.FP32
     res = {}
     if args.which in ("cylinder", "both"):
-        res["cylinder"] = cylinder_sweep(steps=args.steps, precision=prec)
+        res["cylinder"] = cylinder_sweep(thetas=tuple(args.thetas), steps=args.steps, precision=prec)
+        print(json.dumps({"cylinder": res["cylinder"]}), flush=True)
     if args.which in ("plate", "both"):
-        res["plate"] = plate_sweep(steps=args.steps, precision=prec, Wd=args.W)
+        res["plate"] = []
+        for wd in args.W:
+            part = plate_sweep(thetas=tuple(args.thetas), steps=args.steps, precision=prec, Wd=wd)
+            print(json.dumps({"plate_W": wd, "plate": part}), flush=True)
+            res["plate"] += part
     print(json.dumps(res), flush=True)
 
 

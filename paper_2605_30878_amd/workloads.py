@@ -198,7 +198,7 @@ def plate_d2q9(nx: int, ny: int, theta: float, drop_radius: float, W: float = 4.
 
 def porous_d3q19(n: int = 384, sphere_radius: float = 12.0, porosity: float = 0.40,
                  seed: int = 0, precision: int = FP32, front: Optional[float] = None,
-                 max_iter: int = 4000) -> Workload:
+                 max_iter: int = 20000) -> Workload:
     """Dynamic contact line in a random packing of non-overlapping spheres.
 
     Sphere count is chosen so that the continuous solid fraction equals

@@ -76,6 +76,11 @@ def test_call_order_is_enforced():
     assert lib.lbm_device_bytes(h, C.byref(nbytes)) == lbm.OK and nbytes.value > 0
     assert lib.lbm_bind(h, None, nbytes.value, None) == lbm.EINVAL
     assert lib.lbm_step(h, 1) == lbm.ESTATE
+    buf = np.zeros(9 * wl.nodes)
+    ptr = buf.ctypes.data_as(C.POINTER(C.c_double))
+    for field in (lbm.FIELD_N, lbm.FIELD_N_OFFSET, lbm.FIELD_B):
+        assert lib.lbm_set_field(h, field, ptr, buf.size) == lbm.ESTATE
+        assert lib.lbm_read_field(h, field, ptr, buf.size) == lbm.ESTATE
     assert lib.lbm_destroy(h) == lbm.OK
 
 

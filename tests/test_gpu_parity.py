@@ -81,6 +81,20 @@ def test_sphere_d3q19_fp64_parity_ragged():
     _run_pair(wl, [1, 20, 200], TOL64)
 
 
+@pytest.mark.parametrize("shape", [(64, 32, 20), (128, 12, 14)], ids=["xcd_bands", "plain_order"])
+def test_sphere_d3q19_fp64_parity_tiled_colour(shape):
+    """Boxes taken by the z-marching colour kernel (x a multiple of 64, y of
+    4): 64 x 32 x 20 uses the XCD y-band tile order and a ragged last
+    z-chunk, 128 x 12 x 14 the plain order; density ratio 1000."""
+    nx, ny, nz = shape
+    wl = W.Workload(name="d3q19_tile", lattice=W.D3Q19, shape=shape, rho_l=1000.0, rho_g=1.0,
+                    mu_l=10.0, mu_g=0.1, sigma=0.01, W=4.0, theta=60.0,
+                    solids=[W.Solid(0, (nx / 2 - 2.0, ny / 2 - 1.0, 3.0), min(6.5, ny / 2 - 1.0))],
+                    liquid=[W.LiquidRegion("ball", (nx / 2 - 2.0, ny / 2 - 1.0, 8.0), min(6.0, ny / 2 - 1.5),
+                                           width=4.0)])
+    _run_pair(wl, [1, 2, 25, 200], TOL64)
+
+
 def test_sphere_d3q19_fp64_parity_fused_step():
     """A box tiled by the fused one-launch step (64 x 32 x 20: x and y whole
     tiles, z not a whole number of chunks), density ratio 1000."""
@@ -205,23 +219,32 @@ def test_observe_and_mass():
         assert abs(o1["momentum"][a] - oo["momentum"][a]) <= 1e-12 * scale
 
 
-def test_restore_roundtrip_is_bitwise():
-    """Raw state read out and written into a fresh context continues
-    bit-identically (checkpoint / resume)."""
+@pytest.mark.parametrize("prec", [W.FP64, W.FP32, W.FP16_OFS], ids=["f64", "f32", "fp16ofs"])
+def test_restore_roundtrip_is_bitwise(prec):
+    """Raw state (populations as stored offsets, liquid populations, solid
+    phi) read out and written into a fresh context continues bit-identically
+    (checkpoint / resume)."""
     lbm = _lbm()
-    wl = W.sphere_d3q19(32, theta=120.0, precision=W.FP32)
+    wl = W.sphere_d3q19(32, theta=120.0, precision=prec)
     phi0 = W.initial_phi(wl)
     a = lbm.Simulation(wl, phi0)
     a.step(25)
-    N, B, S = a.read(lbm.FIELD_N), a.read(lbm.FIELD_B), a.read(lbm.FIELD_SOLID_PHI)
+    N, B, S = a.read(lbm.FIELD_N_OFFSET), a.read(lbm.FIELD_B), a.read(lbm.FIELD_SOLID_PHI)
     b = lbm.Simulation(wl, phi0)
-    b.set_field(lbm.FIELD_N, N)
+    b.set_field(lbm.FIELD_N_OFFSET, N)
     b.set_field(lbm.FIELD_B, B)
     b.set_field(lbm.FIELD_SOLID_PHI, S)
+    assert np.array_equal(a.read(lbm.FIELD_N_OFFSET), b.read(lbm.FIELD_N_OFFSET))
     a.step(10)
     b.step(10)
-    assert np.array_equal(a.read(lbm.FIELD_N), b.read(lbm.FIELD_N))
+    assert np.array_equal(a.read(lbm.FIELD_N_OFFSET), b.read(lbm.FIELD_N_OFFSET))
     assert np.array_equal(a.read(lbm.FIELD_B), b.read(lbm.FIELD_B))
+    # the absolute populations are a per-direction constant (chi_i, summing
+    # to 1) plus the offsets
+    fluid = (a.read(lbm.FIELD_FLAGS).astype(int) & lbm.FLAG_SOLID) == 0
+    d = a.read(lbm.FIELD_N)[:, fluid] - a.read(lbm.FIELD_N_OFFSET)[:, fluid]
+    assert float(np.max(d.max(axis=1) - d.min(axis=1))) <= 1e-15
+    assert abs(float(d[:, 0].sum()) - 1.0) <= 1e-6
 
 
 def test_nonfinite_is_reported():
