@@ -133,7 +133,10 @@ typedef struct {
 
 /* Validate params and create a context (host memory only).
  * Errors: LBM_EINVAL for W < 4, non-positive densities/viscosities/mobility,
- * tau <= 1/2, alpha outside [0, 1), bad lattice/precision/rule/sizes. */
+ * tau <= 1/2, alpha outside [0, 1), bad lattice/precision/rule/sizes.
+ * Size limits: at most 2^31 - 1 nodes, n[1], n[2] <= 65535, and one field
+ * plane (nodes rounded up to 128, times 8 bytes in FP64 and 4 bytes
+ * otherwise) below 4 GiB: up to 5.4e8 nodes in FP64, 1.07e9 otherwise. */
 int lbm_create(const lbm_params* params, lbm_ctx** out);
 
 /* Rasterise `count` solids (host), classify nodes (solid, ghost = solid with

@@ -20,6 +20,10 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+    # contraction into FMA only within one source expression: a per-node
+    # device function then rounds the same way in every kernel that calls
+    # it (single-run and batched launches give bit-identical runs)
+    "-ffp-contract=on",
     # packed-FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fno-gpu-rdc", "-Wall", "-Wno-unused-result",

@@ -116,6 +116,11 @@ int lbm_create(const lbm_params* P, lbm_ctx** out) {
     lattice_table((int)P->lattice, c->D, c->Q, c->NC, &cv, &w);
     c->n = n;
     c->S = (n + 127) / 128 * 128;   // plane stride: planes of 2-, 4- and 8-byte values stay 256-byte aligned
+    // The kernels address a field plane with 32-bit byte offsets.
+    if ((uint64_t)c->S * std::max(elem_size(P->precision), phi_size(P->precision)) > 0xFFFFFFFFull) {
+        delete c;
+        return fail(nullptr, LBM_EINVAL, "box too large: one field plane must stay below 4 GiB");
+    }
     const double cs2 = 1.0 / 3.0;
     // Colour weights (Eq. A7): chi_0 = alpha, chi_i = (1 - alpha) w_i / (1 - w_0),
     // alpha from M_phi = (dt/2) [sum_i chi_i c_ix^2 + p] at p = 0.

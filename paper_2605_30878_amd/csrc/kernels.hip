@@ -52,6 +52,20 @@ __device__ __forceinline__ void static_for(F&& f) {
     }
 }
 
+// Element idx of a field plane through a 32-bit byte offset from a
+// wave-uniform base: the access compiles to a global load/store with a
+// scalar base address and one VGPR offset, with no 64-bit address
+// arithmetic per access.  Every field plane is below 4 GiB (checked at
+// lbm_create), so idx * sizeof(V) fits in 32 bits.
+template <class V>
+__device__ __forceinline__ V ld(const V* __restrict__ base, uint32_t idx) {
+    return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(V));
+}
+template <class V>
+__device__ __forceinline__ void st(V* __restrict__ base, uint32_t idx, V v) {
+    *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(V)) = v;
+}
+
 // c * v for a lattice component c in {-1, 0, 1}, resolved at compile time.
 template <int C, class T>
 __device__ __forceinline__ T cmul(T v) {
@@ -166,15 +180,21 @@ __device__ __forceinline__ void macro_stage(const T (&N)[L::Q], const T (&ph)[L:
     constexpr T w0 = T(L::w[0]);
     const T phi = ph[0];
     m.phi = phi;
-    // Isotropic stencils: grad = 3 sum w c phi ; lap = 6 sum_{i>0} w (phi_i - phi)
+    // Isotropic stencils, summed over opposite pairs (i, opp i):
+    // grad = 3 sum w c phi = 3 sum_pairs w c_i (phi_i - phi_opp),
+    // lap = 6 sum_{i>0} w (phi_i - phi) = 6 (sum_pairs w (phi_i + phi_opp) - (1 - w0) phi).
     T gx = 0, gy = 0, gz = 0, lap = 0;
     static_for<1, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        constexpr T wi = T(L::w[i]);
-        gx += cmul<L::c[i][0]>(wi * ph[i]);
-        gy += cmul<L::c[i][1]>(wi * ph[i]);
-        gz += cmul<L::c[i][2]>(wi * ph[i]);
-        lap += wi * ph[i];
+        if constexpr (i < L::opp[i]) {
+            constexpr int j = L::opp[i];
+            constexpr T wi = T(L::w[i]);
+            const T d = wi * (ph[i] - ph[j]);
+            if constexpr (L::c[i][0] != 0) gx += cmul<L::c[i][0]>(d);
+            if constexpr (L::c[i][1] != 0) gy += cmul<L::c[i][1]>(d);
+            if constexpr (L::c[i][2] != 0) gz += cmul<L::c[i][2]>(d);
+            lap += wi * (ph[i] + ph[j]);
+        }
     });
     gx *= T(3);
     gy *= T(3);
@@ -189,23 +209,28 @@ __device__ __forceinline__ void macro_stage(const T (&N)[L::Q], const T (&ph)[L:
     const T tau = T(0.5) + T(3) / inv_nu;
     m.rho = rho;
     m.tau = tau;
-    // Moments of N.
+    // Moments of N over opposite pairs: a = n_i + n_opp carries the even
+    // moments (zeroth, second), d = n_i - n_opp the odd one (first).
     T jx = 0, jy = 0, jz = 0, s = 0;
     T pxx = 0, pyy = 0, pzz = 0, pxy = 0, pyz = 0, pxz = 0;
     static_for<1, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-        const T n = N[i];
-        s += n;
-        jx += cmul<cx>(n);
-        jy += cmul<cy>(n);
-        jz += cmul<cz>(n);
-        if constexpr (cx != 0) pxx += n;
-        if constexpr (cy != 0) pyy += n;
-        if constexpr (cz != 0) pzz += n;
-        if constexpr (cx * cy != 0) pxy += cmul<cx * cy>(n);
-        if constexpr (cy * cz != 0) pyz += cmul<cy * cz>(n);
-        if constexpr (cx * cz != 0) pxz += cmul<cx * cz>(n);
+        if constexpr (i < L::opp[i]) {
+            constexpr int j = L::opp[i];
+            constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+            const T a = N[i] + N[j];
+            const T d = N[i] - N[j];
+            s += a;
+            if constexpr (cx != 0) jx += cmul<cx>(d);
+            if constexpr (cy != 0) jy += cmul<cy>(d);
+            if constexpr (cz != 0) jz += cmul<cz>(d);
+            if constexpr (cx != 0) pxx += a;
+            if constexpr (cy != 0) pyy += a;
+            if constexpr (cz != 0) pzz += a;
+            if constexpr (cx * cy != 0) pxy += cmul<cx * cy>(a);
+            if constexpr (cy * cz != 0) pyz += cmul<cy * cz>(a);
+            if constexpr (cx * cz != 0) pxz += cmul<cx * cz>(a);
+        }
     });
     Pi[0] = pxx; Pi[1] = pyy; Pi[2] = pzz; Pi[3] = pxy; Pi[4] = pyz; Pi[5] = pxz;
     // Eq. A15 with u0 = sum c N (the forced u needs F_p(p)); s = sum_{i>0} n_i
@@ -277,23 +302,34 @@ __device__ __forceinline__ void collide_stage(const Macro<T>& m, const T (&Pi)[6
         s5 = omega * (Pi[5] - ux * uz) * T(0.25);
     }
     // Offsets n*_i = N*_i - chi_i.  The rest direction has no stress moment.
+    // For an opposite pair the equilibrium's even part, the forcing's odd
+    // part and the (even) stress projection give
+    //   n*_i, n*_opp = sym +- asym,
+    //   sym = w_i (p/cs^2 - 1.5 u.u + 4.5 (c_i.u)^2) + proj_i,
+    //   asym = w_i (3 c_i.u + 1.5 c_i.a)     (F_i / 2 = 1.5 w_i c_i.a).
     Ns[0] = -(T(1) - w0) * p3 - w0 * T(1.5) * uu;
+    const T A = p3 - T(1.5) * uu;
     static_for<1, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-        constexpr T wi = T(L::w[i]);
-        const T cu = cmul<cx>(ux) + cmul<cy>(uy) + cmul<cz>(uz);
-        const T ca = cmul<cx>(m.a[0]) + cmul<cy>(m.a[1]) + cmul<cz>(m.a[2]);
-        const T neq = wi * (p3 + T(3) * cu + T(4.5) * cu * cu - T(1.5) * uu);
-        // projection onto the stress rows, m_k(i) evaluated at compile time
-        T proj;
-        if constexpr (L::D == 2) {
-            proj = T(cx * cx - cy * cy) * s1 + T(cx * cy) * s2;
-        } else {
-            proj = T(2 * cx * cx - cy * cy - cz * cz) * s1 + T(cy * cy - cz * cz) * s2 + T(cx * cy) * s3 +
-                   T(cy * cz) * s4 + T(cx * cz) * s5;
+        if constexpr (i < L::opp[i]) {
+            constexpr int j = L::opp[i];
+            constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+            constexpr T wi = T(L::w[i]);
+            const T cu = cmul<cx>(ux) + cmul<cy>(uy) + cmul<cz>(uz);
+            const T ca = cmul<cx>(m.a[0]) + cmul<cy>(m.a[1]) + cmul<cz>(m.a[2]);
+            // projection onto the stress rows, m_k(i) evaluated at compile time
+            T proj;
+            if constexpr (L::D == 2) {
+                proj = T(cx * cx - cy * cy) * s1 + T(cx * cy) * s2;
+            } else {
+                proj = T(2 * cx * cx - cy * cy - cz * cz) * s1 + T(cy * cy - cz * cz) * s2 + T(cx * cy) * s3 +
+                       T(cy * cz) * s4 + T(cx * cz) * s5;
+            }
+            const T sym = wi * (A + T(4.5) * cu * cu) + proj;
+            const T asym = wi * (T(3) * cu + T(1.5) * ca);
+            Ns[i] = sym + asym;
+            Ns[j] = sym - asym;
         }
-        Ns[i] = neq + T(1.5) * wi * ca + proj;   // F_i / 2 = (3 w_i a.c_i) / 2
     });
     // Recolouring vector: normal where |grad phi| is resolved, amplitude
     // clamped at 0 where phi leaves [0, 1].
@@ -311,8 +347,8 @@ __device__ __forceinline__ void collide_stage(const Macro<T>& m, const T (&Pi)[6
 }
 
 // Neighbour index tables of a node: nb[i] = index of x + c_i (periodic).
-template <class L>
-__device__ __forceinline__ void neighbours(int ix, int iy, int iz, int nx, int ny, int nz, int64_t (&nb)[L::Q]) {
+template <class L, class I>
+__device__ __forceinline__ void neighbours(int ix, int iy, int iz, int nx, int ny, int nz, I (&nb)[L::Q]) {
     const int xm = ix == 0 ? nx - 1 : ix - 1, xp = ix == nx - 1 ? 0 : ix + 1;
     const int ym = iy == 0 ? ny - 1 : iy - 1, yp = iy == ny - 1 ? 0 : iy + 1;
     int zm = 0, zp = 0;
@@ -326,7 +362,7 @@ __device__ __forceinline__ void neighbours(int ix, int iy, int iz, int nx, int n
         const int X = cx == 0 ? ix : (cx > 0 ? xp : xm);
         const int Y = cy == 0 ? iy : (cy > 0 ? yp : ym);
         const int Z = cz == 0 ? iz : (cz > 0 ? zp : zm);
-        nb[i] = (int64_t)X + (int64_t)nx * ((int64_t)Y + (int64_t)ny * Z);
+        nb[i] = (I)X + (I)nx * ((I)Y + (I)ny * (I)Z);
     });
 }
 
@@ -402,24 +438,24 @@ __device__ __forceinline__ T compact_term(T n, T phi_src, T gx, T gy, T gz, T p,
 template <class L, class T, class SN, int I>
 __device__ __forceinline__ T compact_B(const SN* __restrict__ N, const T* __restrict__ phi_prev,
                                        const T* __restrict__ G, const uint8_t* __restrict__ flags,
-                                       const KParams<T, L::Q>& P, int64_t y, const int64_t (&nb)[L::Q],
+                                       const KParams<T, L::Q>& P, uint32_t y, const uint32_t (&nb)[L::Q],
                                        bool near_solid) {
     const int64_t S = P.S;
-    const T n = NStore<T, SN>::dec(N[(int64_t)I * S + y], P.n_s);
+    const T n = NStore<T, SN>::dec(ld(N + (int64_t)I * S, y), P.n_s);
     if constexpr (I == 0) {
-        return phi_prev[y] * (P.chi[0] + n);
+        return ld(phi_prev, y) * (P.chi[0] + n);
     } else {
         constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
-        int64_t src = nb[L::opp[I]];
+        uint32_t src = nb[L::opp[I]];
         T sgn = T(1);
-        if (near_solid && (flags[src] & FLAG_SOLID)) {
+        if (near_solid && (ld(flags, src) & FLAG_SOLID)) {
             src = y;
             sgn = T(-1);
         }
-        const T gx = cx != 0 ? G[src] : T(0);
-        const T gy = cy != 0 ? G[S + src] : T(0);
-        const T gz = cz != 0 ? G[2 * S + src] : T(0);
-        return compact_term<L, T, I>(n, phi_prev[src], gx, gy, gz, G[(int64_t)GRec<L>::P * S + src], sgn, P);
+        const T gx = cx != 0 ? ld(G, src) : T(0);
+        const T gy = cy != 0 ? ld(G + S, src) : T(0);
+        const T gz = cz != 0 ? ld(G + 2 * S, src) : T(0);
+        return compact_term<L, T, I>(n, ld(phi_prev, src), gx, gy, gz, ld(G + (int64_t)GRec<L>::P * S, src), sgn, P);
     }
 }
 
@@ -450,10 +486,10 @@ __device__ __forceinline__ void colour_compact_node(const SN* __restrict__ N, co
                                                     const T* __restrict__ G, const uint8_t* __restrict__ flags,
                                                     T* __restrict__ phi, const KParams<T, L::Q>& P, int ix, int iy,
                                                     int iz) {
-    const int64_t x = (int64_t)ix + (int64_t)P.nx * ((int64_t)iy + (int64_t)P.ny * iz);
-    const uint8_t f = flags[x];
+    const uint32_t x = (uint32_t)ix + (uint32_t)P.nx * ((uint32_t)iy + (uint32_t)P.ny * (uint32_t)iz);
+    const uint8_t f = ld(flags, x);
     if (f & FLAG_SOLID) return;
-    int64_t nb[L::Q];
+    uint32_t nb[L::Q];
     neighbours<L>(ix, iy, iz, P.nx, P.ny, P.nz, nb);
     const bool near = (f & FLAG_NEAR_SOLID) != 0;
     T acc = 0;
@@ -461,7 +497,7 @@ __device__ __forceinline__ void colour_compact_node(const SN* __restrict__ N, co
         constexpr int i = decltype(ic)::value;
         acc += compact_B<L, T, SN, i>(N, phi_prev, G, flags, P, x, nb, near);
     });
-    phi[x] = acc;
+    st(phi, x, acc);
 }
 
 template <class L, class T, class SN>
@@ -553,10 +589,10 @@ __global__ __launch_bounds__(CTX * CTY) void k_colour_tile(const SN* __restrict_
     colour_tile_load<T>(sm, z0 - 1, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
     colour_tile_load<T>(sm, z0, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
     for (int z = z0; z < z1; z++) {
-        const int64_t x = (int64_t)(x0 + tx) + (int64_t)P.nx * ((int64_t)(y0 + ty) + (int64_t)P.ny * z);
+        const uint32_t x = (uint32_t)(x0 + tx) + (uint32_t)P.nx * ((uint32_t)(y0 + ty) + (uint32_t)P.ny * (uint32_t)z);
         SN raw[19];
 #pragma unroll
-        for (int i = 0; i < 19; i++) raw[i] = N[(int64_t)i * S + x];
+        for (int i = 0; i < 19; i++) raw[i] = ld(N + (int64_t)i * S, x);
         colour_tile_load<T>(sm, z + 1, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
         __syncthreads();
         const int s0 = slot3(z), sx = tx + 1, sy = ty + 1;
@@ -585,7 +621,7 @@ __global__ __launch_bounds__(CTX * CTY) void k_colour_tile(const SN* __restrict_
                     acc += compact_term<L, T, i>(n, sm.rec[sl][0][qy][qx], gx, gy, gz, sm.rec[sl][4][qy][qx], sgn, P);
                 }
             });
-            phi[x] = acc;
+            st(phi, x, acc);
         }
         __syncthreads();
     }
@@ -603,13 +639,13 @@ __global__ __launch_bounds__(256) void k_compact_B_plane(const SN* __restrict__ 
         out[r.x] = 0.0;
         return;
     }
-    int64_t nb[L::Q];
+    uint32_t nb[L::Q];
     neighbours<L>(r.ix, r.iy, r.iz, P.nx, P.ny, P.nz, nb);
     const bool near = (f & FLAG_NEAR_SOLID) != 0;
     T v = 0;
     static_for<0, L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        if (i == dir) v = compact_B<L, T, SN, i>(N, phi_prev, G, flags, P, r.x, nb, near);
+        if (i == dir) v = compact_B<L, T, SN, i>(N, phi_prev, G, flags, P, (uint32_t)r.x, nb, near);
     });
     out[r.x] = (double)v;
 }
@@ -660,17 +696,18 @@ __device__ __forceinline__ void collide_node(const SN* __restrict__ Nsrc, SN* __
                                              const uint8_t* __restrict__ flags, const KParams<T, L::Q>& P, int ix,
                                              int iy, int iz) {
     constexpr int Q = L::Q;
-    const int64_t x = (int64_t)ix + (int64_t)P.nx * ((int64_t)iy + (int64_t)P.ny * iz);
-    const uint8_t f = flags[x];
+    const uint32_t x = (uint32_t)ix + (uint32_t)P.nx * ((uint32_t)iy + (uint32_t)P.ny * (uint32_t)iz);
+    const uint8_t f = ld(flags, x);
     if (f & FLAG_SOLID) return;
-    int64_t nb[Q];
+    uint32_t nb[Q];
     neighbours<L>(ix, iy, iz, P.nx, P.ny, P.nz, nb);
     using NS = NStore<T, SN>;
+    const int64_t S = P.S;
     T N[Q], ph[Q];
 #pragma unroll
-    for (int i = 0; i < Q; i++) N[i] = NS::dec(Nsrc[(int64_t)i * P.S + x], P.n_s);
+    for (int i = 0; i < Q; i++) N[i] = NS::dec(ld(Nsrc + (int64_t)i * S, x), P.n_s);
 #pragma unroll
-    for (int i = 0; i < Q; i++) ph[i] = phi[nb[i]];
+    for (int i = 0; i < Q; i++) ph[i] = ld(phi, nb[i]);
     Macro<T> m;
     T Pi[6];
     macro_stage<L, T>(N, ph, P, m, Pi);
@@ -685,20 +722,19 @@ __device__ __forceinline__ void collide_node(const SN* __restrict__ Nsrc, SN* __
         closure -= NS::off(e[i]);
     }
     e[0] = NS::enc_off(closure);
-    const int64_t S = P.S;
     if (f & FLAG_NEAR_SOLID) {
         static_for<0, Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            if (flags[nb[i]] & FLAG_SOLID) Ndst[(int64_t)L::opp[i] * S + x] = e[i];
-            else Ndst[(int64_t)i * S + nb[i]] = e[i];
+            if (ld(flags, nb[i]) & FLAG_SOLID) st(Ndst + (int64_t)L::opp[i] * S, x, e[i]);
+            else st(Ndst + (int64_t)i * S, nb[i], e[i]);
         });
     } else {
 #pragma unroll
-        for (int i = 0; i < Q; i++) Ndst[(int64_t)i * S + nb[i]] = e[i];
+        for (int i = 0; i < Q; i++) st(Ndst + (int64_t)i * S, nb[i], e[i]);
     }
 #pragma unroll
-    for (int a = 0; a < L::D; a++) Gdst[(int64_t)a * S + x] = G[a];
-    Gdst[(int64_t)GRec<L>::P * S + x] = m.p;
+    for (int a = 0; a < L::D; a++) st(Gdst + (int64_t)a * S, x, G[a]);
+    st(Gdst + (int64_t)GRec<L>::P * S, x, m.p);
 }
 
 // One thread per node of an x-row; grid (x-blocks, ny, nz).
@@ -964,13 +1000,13 @@ __global__ __launch_bounds__(256) void k_ghost_direct(const int32_t* __restrict_
             v = phiA[c];
         } else {
             const int ix = c % P.nx, iy = (c / P.nx) % P.ny, iz = c / (P.nx * P.ny);
-            int64_t nb[L::Q];
+            uint32_t nb[L::Q];
             neighbours<L>(ix, iy, iz, P.nx, P.ny, P.nz, nb);
             const bool near = (flags[c] & FLAG_NEAR_SOLID) != 0;
             T acc = 0;
             static_for<0, L::Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
-                acc += compact_B<L, T, SN, i>(N, phiA, G, flags, P, c, nb, near);
+                acc += compact_B<L, T, SN, i>(N, phiA, G, flags, P, (uint32_t)c, nb, near);
             });
             v = acc;
         }
@@ -1261,8 +1297,14 @@ static inline int row_block(int nx) {
     return b > LBM_COLLIDE_BX ? LBM_COLLIDE_BX : b;
 }
 
+// Row kernels run in plain row-major block order: a y-band order per XCD
+// (each XCD's L2 holding a stencil's y +- 1 rows) measured slower on gfx950
+// for both row kernels.  LBM_XCD_BANDS=1 builds it for comparison.
 #ifndef LBM_XCD_BANDS
-#define LBM_XCD_BANDS 1
+#define LBM_XCD_BANDS 0
+#endif
+#ifndef LBM_TILE_BANDS
+#define LBM_TILE_BANDS 1
 #endif
 
 static inline RowSched row_sched(const StepParams& p, int bx) {
@@ -1299,7 +1341,7 @@ static inline TileSched tile_sched(const StepParams& p) {
     TileSched s;
     s.xt = p.nx / CTX;
     s.yt = p.ny / CTY;
-    s.band = (LBM_XCD_BANDS && s.yt % 8 == 0) ? s.yt / 8 : 0;
+    s.band = (LBM_TILE_BANDS && s.yt % 8 == 0) ? s.yt / 8 : 0;
     return s;
 }
 

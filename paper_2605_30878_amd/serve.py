@@ -149,7 +149,7 @@ class Server:
                         obs = sim.observe()
                         state = None
                         if self.keep_state:
-                            state = {"N": sim.read(lbm.FIELD_N), "B": sim.read(lbm.FIELD_B)}
+                            state = {"N": sim.read(lbm.FIELD_N_OFFSET), "B": sim.read(lbm.FIELD_B)}
                         results.append(Result(r.rid, r.arrival, adm, time.monotonic() - t0, r.workload.nodes,
                                               r.steps, obs, state))
                         sim.close()

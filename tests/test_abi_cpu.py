@@ -58,6 +58,15 @@ def test_create_rejects_bad_box():
     p.n[2] = 1
     p.n[0] = 0
     assert lbm.load_library().lbm_create(C.byref(p), C.byref(h)) == lbm.EINVAL
+    # one FP32 field plane of more than 4 GiB (2^30 + 2^20 nodes)
+    p.precision = W.FP32
+    p.n[0], p.n[1] = 1 << 15, (1 << 15) + 32
+    assert lbm.load_library().lbm_create(C.byref(p), C.byref(h)) == lbm.EINVAL
+    p.n[1] = 1 << 14   # 2^29 nodes: a 2 GiB plane is accepted in FP32 ...
+    assert lbm.load_library().lbm_create(C.byref(p), C.byref(h)) == lbm.OK
+    assert lbm.load_library().lbm_destroy(h) == lbm.OK
+    p.precision = W.FP64   # ... and is a 4 GiB plane in FP64
+    assert lbm.load_library().lbm_create(C.byref(p), C.byref(h)) == lbm.EINVAL
 
 
 def test_call_order_is_enforced():
