@@ -177,6 +177,7 @@ def main() -> int:
                     "mu_ratio": 10, "theta_deg": 45, "body_accel": 1e-6, "storage": args.precision,
                     "n_fluid": n_fluid, "n_ghost": obs1["n_ghost"],
                     "porosity_nodes": round(n_fluid / wl.nodes, 4),
+                    "ghost_probe": "fluid corners" if wl.probe else "all corners",
                     "mflups": round(n_fluid * args.steps / (dt * 1e6), 2)}),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

@@ -65,6 +65,16 @@ enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_OFS = 2, LBM_BF16_OFS = 3 };
  * and reads N once.  Both compute the same update. */
 #define LBM_OPT_FUSED 1
 
+/* Probe interpolation of the ghost rule.  By default phi_F at
+ * x_F = x_G + n_s (text before Eq. 8) interpolates all 2^D corners, solid
+ * ones with their current value (ghosts: last step's; deeper solid nodes:
+ * (1 + cos theta)/2).  With LBM_OPT_FLUID_PROBE only the fluid corners take
+ * part, their weights rescaled to sum 1; a probe with no fluid corner keeps
+ * all corners.  In narrow gaps between solids (packings) the default lets
+ * probes read the far solid's (1 + cos theta)/2 and, below 90 degrees at
+ * density ratio 10, drives gas nodes there unstable within ~200 steps. */
+#define LBM_OPT_FLUID_PROBE 2
+
 /* Ghost-node rule: Eq. 9 (this paper) or Eq. 10 (Fakhari et al.). */
 enum { LBM_GHOST_EQ9 = 0, LBM_GHOST_FAKHARI = 1 };
 
@@ -98,7 +108,8 @@ typedef struct {
     uint32_t precision;     /* LBM_FP64 ... */
     uint32_t ghost_rule;    /* LBM_GHOST_EQ9 or LBM_GHOST_FAKHARI */
     int32_t n[3];           /* box nodes; n[2] must be 1 for D2Q9 */
-    int32_t options;        /* bit 0 (LBM_OPT_FUSED): use the fused one-launch D3Q19 step where it applies */
+    int32_t options;        /* bit 0 (LBM_OPT_FUSED): use the fused one-launch D3Q19 step where it applies;
+                               bit 1 (LBM_OPT_FLUID_PROBE): fluid-only probe interpolation */
     double rho_l, rho_g;    /* liquid (phi = 1) and gas (phi = 0) densities, > 0 */
     double mu_l, mu_g;      /* dynamic viscosities, > 0 */
     double sigma;           /* surface tension, >= 0 */

@@ -54,7 +54,9 @@ typedef struct {
     double g[3];          /* body acceleration: F_b = rho g (Eq. 2) */
     double theta_deg;     /* contact angle through the liquid (Eq. 7) */
     int32_t ghost_rule;   /* 0 = Eq. 9, 1 = Eq. 10 (Fakhari et al.) */
-    int32_t pad;
+    int32_t probe;        /* corners of the probe interpolation: 0 = all eight
+                             (solid ones from the snapshot), 1 = fluid ones
+                             only, weights rescaled to sum 1 */
 } orc_params;
 
 typedef struct {
@@ -558,6 +560,18 @@ void* orc_create(const orc_params* P, const orc_solid* solids, int nsolids,
             if (D == 3) wgt *= (bz ? fr[2] : 1.0 - fr[2]);
             s->corner[ng * 8 + k] = node_id(s, cx, cy, cz);
             s->cw[ng * 8 + k] = wgt;
+        }
+        /* READING (alternative probe, option): phi_F is meant to be the fluid's
+         * colour at x_F (the text before Eq. 8 places x_F in the fluid), so
+         * only fluid corners take part, their weights rescaled to sum to 1;
+         * a probe with no fluid corner keeps all corners. */
+        if (P->probe == 1) {
+            double wf = 0.0;
+            for (int k = 0; k < nc; k++)
+                if (!s->solid[s->corner[ng * 8 + k]]) wf += s->cw[ng * 8 + k];
+            if (wf > 0.0)
+                for (int k = 0; k < nc; k++)
+                    s->cw[ng * 8 + k] = s->solid[s->corner[ng * 8 + k]] ? 0.0 : s->cw[ng * 8 + k] / wf;
         }
         s->ghost[ng++] = id;
     }

@@ -308,6 +308,18 @@ int lbm_set_geometry(lbm_ctx* c, const lbm_solid* solids, int32_t count) {
             c->g_w[(size_t)k * ng + g] = wt;
             if (c->flags[cid] & FLAG_SOLID) mask |= (uint8_t)(1u << k);
         }
+        if (c->P.options & LBM_OPT_FLUID_PROBE) {
+            // phi_F from the fluid corners only, weights rescaled to sum 1
+            // (a probe with no fluid corner keeps all eight).
+            double wf = 0.0;
+            for (int k = 0; k < NC; k++)
+                if (!((mask >> k) & 1u)) wf += c->g_w[(size_t)k * ng + g];
+            if (wf > 0.0)
+                for (int k = 0; k < NC; k++) {
+                    double& w = c->g_w[(size_t)k * ng + g];
+                    w = ((mask >> k) & 1u) ? 0.0 : w / wf;
+                }
+        }
         c->g_node[g] = (int32_t)id;
         c->g_mask[g] = mask;
     }

@@ -552,6 +552,45 @@ __device__ __forceinline__ void tile_index(const TileSched& s, int& bx, int& by,
     }
 }
 
+// LBM_COLOUR_PIPE=1 issues the loads of the next plane before the current
+// plane's arithmetic; it needs ~50 more VGPRs and measured no faster.
+#ifndef LBM_COLOUR_PIPE
+#define LBM_COLOUR_PIPE 0
+#endif
+
+// The record and flags of plane z for the tile and its ring, staged through
+// registers: each thread fetches up to two of the CRX * CRY entries (one
+// plane ahead of use), then writes them to LDS.
+template <class T>
+struct TileRec {
+    T v[2][5];
+    uint8_t f[2];
+};
+
+template <class T>
+__device__ __forceinline__ void colour_tile_fetch(TileRec<T>& r, int z, int x0, int y0,
+                                                  const T* __restrict__ phi_prev, const T* __restrict__ G,
+                                                  const uint8_t* __restrict__ flags, int nx, int ny, int nz,
+                                                  int64_t S) {
+    const int Z = wrapc(z, nz);
+#pragma unroll
+    for (int e = 0; e < 2; e++) {
+        const int k = threadIdx.x + e * CTX * CTY;
+        if (k < CRX * CRY) {
+            const int lx = k % CRX, ly = k / CRX;
+            const int X = wrapc(x0 + lx - 1, nx), Y = wrapc(y0 + ly - 1, ny);
+            const uint32_t id = (uint32_t)X + (uint32_t)nx * ((uint32_t)Y + (uint32_t)ny * (uint32_t)Z);
+            r.v[e][0] = ld(phi_prev, id);
+            r.v[e][1] = ld(G, id);
+            r.v[e][2] = ld(G + S, id);
+            r.v[e][3] = ld(G + 2 * S, id);
+            r.v[e][4] = ld(G + 3 * S, id);
+            r.f[e] = ld(flags, id);
+        }
+    }
+}
+
+// Fetch and store in one pass (one entry live at a time).
 template <class T>
 __device__ __forceinline__ void colour_tile_load(ColourSmem<T>& sm, int z, int x0, int y0,
                                                  const T* __restrict__ phi_prev, const T* __restrict__ G,
@@ -562,13 +601,28 @@ __device__ __forceinline__ void colour_tile_load(ColourSmem<T>& sm, int z, int x
     for (int k = threadIdx.x; k < CRX * CRY; k += CTX * CTY) {
         const int lx = k % CRX, ly = k / CRX;
         const int X = wrapc(x0 + lx - 1, nx), Y = wrapc(y0 + ly - 1, ny);
-        const int64_t id = (int64_t)X + (int64_t)nx * ((int64_t)Y + (int64_t)ny * Z);
-        sm.rec[sl][0][ly][lx] = phi_prev[id];
-        sm.rec[sl][1][ly][lx] = G[id];
-        sm.rec[sl][2][ly][lx] = G[S + id];
-        sm.rec[sl][3][ly][lx] = G[2 * S + id];
-        sm.rec[sl][4][ly][lx] = G[3 * S + id];
-        sm.fl[sl][ly][lx] = flags[id];
+        const uint32_t id = (uint32_t)X + (uint32_t)nx * ((uint32_t)Y + (uint32_t)ny * (uint32_t)Z);
+        sm.rec[sl][0][ly][lx] = ld(phi_prev, id);
+        sm.rec[sl][1][ly][lx] = ld(G, id);
+        sm.rec[sl][2][ly][lx] = ld(G + S, id);
+        sm.rec[sl][3][ly][lx] = ld(G + 2 * S, id);
+        sm.rec[sl][4][ly][lx] = ld(G + 3 * S, id);
+        sm.fl[sl][ly][lx] = ld(flags, id);
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void colour_tile_store(ColourSmem<T>& sm, const TileRec<T>& r, int z) {
+    const int sl = slot3(z);
+#pragma unroll
+    for (int e = 0; e < 2; e++) {
+        const int k = threadIdx.x + e * CTX * CTY;
+        if (k < CRX * CRY) {
+            const int lx = k % CRX, ly = k / CRX;
+#pragma unroll
+            for (int q = 0; q < 5; q++) sm.rec[sl][q][ly][lx] = r.v[e][q];
+            sm.fl[sl][ly][lx] = r.f[e];
+        }
     }
 }
 
@@ -586,15 +640,36 @@ __global__ __launch_bounds__(CTX * CTY) void k_colour_tile(const SN* __restrict_
     const int z1 = min(z0 + zc, P.nz);
     const int tx = threadIdx.x % CTX, ty = threadIdx.x / CTX;
     const int64_t S = P.S;
+    const uint32_t xy = (uint32_t)(x0 + tx) + (uint32_t)P.nx * (uint32_t)(y0 + ty);
+    const uint32_t plane = (uint32_t)P.nx * (uint32_t)P.ny;
     colour_tile_load<T>(sm, z0 - 1, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
     colour_tile_load<T>(sm, z0, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
-    for (int z = z0; z < z1; z++) {
-        const uint32_t x = (uint32_t)(x0 + tx) + (uint32_t)P.nx * ((uint32_t)(y0 + ty) + (uint32_t)P.ny * (uint32_t)z);
-        SN raw[19];
+    SN raw[19];
+#if LBM_COLOUR_PIPE
+    TileRec<T> rec;
+    SN nxt[19];
+    colour_tile_fetch<T>(rec, z0 + 1, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
 #pragma unroll
-        for (int i = 0; i < 19; i++) raw[i] = ld(N + (int64_t)i * S, x);
+    for (int i = 0; i < 19; i++) raw[i] = ld(N + (int64_t)i * S, xy + plane * (uint32_t)z0);
+#endif
+    for (int z = z0; z < z1; z++) {
+#if LBM_COLOUR_PIPE
+        // the record of plane z + 1 (fetched during the previous plane) into
+        // LDS, then the loads of the next plane before this plane's arithmetic
+        colour_tile_store<T>(sm, rec, z + 1);
+        __syncthreads();
+        if (z + 1 < z1) {
+#pragma unroll
+            for (int i = 0; i < 19; i++) nxt[i] = ld(N + (int64_t)i * S, xy + plane * (uint32_t)(z + 1));
+        }
+        colour_tile_fetch<T>(rec, z + 2, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
+#else
+        // N of plane z, the record of plane z + 1 into LDS
+#pragma unroll
+        for (int i = 0; i < 19; i++) raw[i] = ld(N + (int64_t)i * S, xy + plane * (uint32_t)z);
         colour_tile_load<T>(sm, z + 1, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
         __syncthreads();
+#endif
         const int s0 = slot3(z), sx = tx + 1, sy = ty + 1;
         const uint8_t f = sm.fl[s0][sy][sx];
         if (!(f & FLAG_SOLID)) {
@@ -621,9 +696,13 @@ __global__ __launch_bounds__(CTX * CTY) void k_colour_tile(const SN* __restrict_
                     acc += compact_term<L, T, i>(n, sm.rec[sl][0][qy][qx], gx, gy, gz, sm.rec[sl][4][qy][qx], sgn, P);
                 }
             });
-            st(phi, x, acc);
+            st(phi, xy + plane * (uint32_t)z, acc);
         }
         __syncthreads();
+#if LBM_COLOUR_PIPE
+#pragma unroll
+        for (int i = 0; i < 19; i++) raw[i] = nxt[i];
+#endif
     }
 }
 

@@ -50,7 +50,8 @@ def plate_case(theta: float, rule: int, nx: int = 500, ny: int = 300, area: floa
                       mobility=0.02, theta=theta,
                       solids=[W.Solid(1, (0.0, wall, 0.0), normal=(0.0, 1.0, 0.0)),
                               W.Solid(1, (0.0, ny - 1.5, 0.0), normal=(0.0, -1.0, 0.0))],
-                      liquid=[W.LiquidRegion("ball", (nx / 2.0, centre_y, 0.0), Rc, width=Wd)],
+                      liquid=[W.LiquidRegion("ball", (nx / 2.0, centre_y, 0.0), Rc, width=Wd,
+                                             periodic=(True, False, True))],
                       precision=precision, ghost_rule=rule)
 
 

@@ -43,7 +43,8 @@ class Solid:
 class LiquidRegion:
     """A liquid (phi = 1) region with a tanh edge of the given width.
 
-    kind "ball": |x - center| < radius.
+    kind "ball": |x - center| < radius (periodic minimum image along the axes
+    in `periodic`; plain distance along the others, e.g. across walls).
     kind "slab": lo <= x_axis < hi along `axis` (periodic distance).
     kind "below": x_axis < lo along `axis`.
     """
@@ -55,6 +56,7 @@ class LiquidRegion:
     lo: float = 0.0
     hi: float = 0.0
     width: float = 4.0
+    periodic: Tuple[bool, bool, bool] = (True, True, True)
 
 
 @dataclasses.dataclass
@@ -76,6 +78,7 @@ class Workload:
     precision: int = FP64
     steps: int = 1000
     ghost_rule: int = 0
+    probe: int = 0   # 0: probe interpolation over all corners; 1: fluid corners only
 
     @property
     def nodes(self) -> int:
@@ -109,10 +112,11 @@ def initial_phi(wl: Workload) -> np.ndarray:
     pos = (x, y, z)
     for reg in wl.liquid:
         if reg.kind == "ball":
-            dx = _periodic_delta(x, reg.center[0], nx)
-            dy = _periodic_delta(y, reg.center[1], ny)
+            px, py, pz = reg.periodic
+            dx = _periodic_delta(x, reg.center[0], nx) if px else x - reg.center[0]
+            dy = _periodic_delta(y, reg.center[1], ny) if py else y - reg.center[1]
             if wl.lattice == D3Q19:
-                dz = _periodic_delta(z, reg.center[2], nz)
+                dz = _periodic_delta(z, reg.center[2], nz) if pz else z - reg.center[2]
             else:
                 dz = 0.0 * z
             s = reg.radius - np.sqrt(dx * dx + dy * dy + dz * dz)
@@ -198,14 +202,18 @@ def plate_d2q9(nx: int, ny: int, theta: float, drop_radius: float, W: float = 4.
 
 def porous_d3q19(n: int = 384, sphere_radius: float = 12.0, porosity: float = 0.40,
                  seed: int = 0, precision: int = FP32, front: Optional[float] = None,
-                 max_iter: int = 20000) -> Workload:
+                 max_iter: int = 20000, probe: int = 1) -> Workload:
     """Dynamic contact line in a random packing of non-overlapping spheres.
 
     Sphere count is chosen so that the continuous solid fraction equals
     1 - porosity; centres start uniform (seeded) and are pushed apart under the
     periodic minimum image until no pair overlaps.  The wetting liquid
     (theta = 45 deg) fills x < front with tanh interfaces at x = front and
-    x = 0; rho_l/rho_g = 10, mu_l/mu_g = 10, body acceleration (1e-6, 0, 0)."""
+    x = 0; rho_l/rho_g = 10, mu_l/mu_g = 10, body acceleration (1e-6, 0, 0).
+    The ghost-rule probe interpolates fluid corners only (probe = 1): with
+    all corners, probes in the gaps between touching spheres read the far
+    solid's (1 + cos theta)/2 and the run diverges within a few hundred steps
+    (oracle and library alike)."""
     centres = sphere_packing(n, sphere_radius, 1.0 - porosity, seed, max_iter)
     solids = [Solid(0, tuple(float(v) for v in c), sphere_radius) for c in centres]
     front = n / 4.0 if front is None else front
@@ -214,7 +222,7 @@ def porous_d3q19(n: int = 384, sphere_radius: float = 12.0, porosity: float = 0.
         rho_l=10.0, rho_g=1.0, mu_l=1.0, mu_g=0.1, sigma=0.01, W=4.0, mobility=0.02,
         g=(1e-6, 0.0, 0.0), theta=45.0, solids=solids,
         liquid=[LiquidRegion("slab", axis=0, lo=0.0, hi=front, width=4.0)],
-        precision=precision, steps=50000)
+        precision=precision, steps=50000, probe=probe)
 
 
 def sphere_packing(n: int, radius: float, solid_fraction: float, seed: int,

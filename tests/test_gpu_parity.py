@@ -161,9 +161,23 @@ def test_porous_packing_fp64_parity():
     """A seeded packing of non-overlapping spheres (solid fraction 0.6, many
     ghosts, spheres across the periodic edges), wetting liquid in a slab,
     density ratio 10, body force along x."""
-    wl = W.porous_d3q19(n=40, sphere_radius=5.0, porosity=0.40, seed=0, precision=W.FP64, front=10.0)
+    wl = W.porous_d3q19(n=40, sphere_radius=5.0, porosity=0.40, seed=0, precision=W.FP64, front=10.0, probe=0)
     wl = wl.with_(g=(1e-5, 0.0, 0.0))
     _run_pair(wl, [1, 30], TOL64)
+
+
+def test_porous_fluid_probe_fp64_parity():
+    """The same packing with the fluid-only probe interpolation (the porous
+    workload's setting), which keeps the wetting (45 degree) run stable:
+    300 steps against the oracle."""
+    wl = W.porous_d3q19(n=40, sphere_radius=5.0, porosity=0.40, seed=0, precision=W.FP64, front=10.0, probe=1)
+    wl = wl.with_(g=(1e-5, 0.0, 0.0))
+    _run_pair(wl, [1, 30, 300], TOL64)
+
+
+@pytest.mark.parametrize("theta", [30.0, 150.0])
+def test_cylinder_fluid_probe_fp64_parity(theta):
+    _run_pair(W.cylinder_d2q9_128(theta=theta).with_(probe=1), [1, 50, 500], TOL64)
 
 
 def test_sphere_d3q19_fp32_short_against_oracle():

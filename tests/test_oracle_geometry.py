@@ -110,3 +110,33 @@ def test_flat_wall_probe_is_a_node():
         y = ids[g] // nx
         want_y = 1 if y == 0 else wl.shape[1] - 2
         assert corners[g, k] == ids[g] % nx + nx * want_y
+
+
+@pytest.mark.parametrize("wl", [W.cylinder_d2q9_128(), W.sphere_d3q19(64),
+                                W.porous_d3q19(n=40, sphere_radius=5.0, precision=W.FP64, front=10.0)],
+                         ids=["cyl128", "sphere64", "porous40"])
+def test_fluid_only_probe_weights(wl):
+    """The fluid-only probe (option): solid corners get weight 0 and the fluid
+    corners keep their bi/trilinear weights in proportion, summing to 1; a
+    probe whose corners are all fluid is unchanged, and one with no fluid
+    corner keeps the plain weights."""
+    a = oracle.OracleSim(wl.with_(probe=0), W.initial_phi(wl))
+    b = oracle.OracleSim(wl.with_(probe=1), W.initial_phi(wl))
+    ids_a, _, corners, wa = a.ghosts()
+    ids_b, _, corners_b, wb = b.ghosts()
+    assert np.array_equal(ids_a, ids_b) and np.array_equal(corners, corners_b)
+    solid = a.get(oracle.F_SOLID) > 0.5
+    nc = 2 ** (3 if wl.lattice == W.D3Q19 else 2)
+    cs = solid[corners[:, :nc]]
+    wa, wb = wa[:, :nc], wb[:, :nc]
+    fluid_w = np.where(cs, 0.0, wa).sum(axis=1)
+    has_fluid = fluid_w > 0
+    assert np.allclose(wb.sum(axis=1), 1.0, atol=1e-15)
+    assert np.all(wb[has_fluid][cs[has_fluid]] == 0.0)
+    ratio = np.where(cs, 0.0, wa)[has_fluid] / fluid_w[has_fluid, None]
+    assert np.allclose(wb[has_fluid], ratio, atol=1e-15)
+    all_fluid = ~cs.any(axis=1)
+    assert np.array_equal(wb[all_fluid], wa[all_fluid])
+    assert np.array_equal(wb[~has_fluid], wa[~has_fluid])
+    # the rescaling is exercised
+    assert (has_fluid & ~all_fluid).sum() > 0
