@@ -13,6 +13,7 @@ import csv
 import hashlib
 import json
 import os
+import re
 import sys
 from collections import defaultdict
 
@@ -27,10 +28,53 @@ def kernel_source_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+def _itanium_short(base: str) -> str:
+    """lbm::name<args> from an Itanium-mangled kernel name (the tracer leaves
+    names with _Float16 / __bf16 arguments mangled): nested-name components,
+    then lattice, float, double, _Float16, __bf16 and integer arguments."""
+    i, comps = 3, []
+    while i < len(base) and base[i].isdigit():
+        j = i
+        while base[j].isdigit():
+            j += 1
+        n = int(base[i:j])
+        comps.append(base[j:j + n])
+        i = j + n
+    args = ""
+    if i < len(base) and base[i] == "I":
+        rest, k, toks = base[i + 1:], 0, []
+        while k < len(rest) and rest[k] != "E":
+            m = re.match(r"NS_(\d+)", rest[k:])
+            if m:
+                L = int(m.group(1))
+                s = k + m.end()
+                toks.append(rest[s:s + L])
+                k = s + L + 1
+            elif rest.startswith("DF16_", k):
+                toks.append("_Float16")
+                k += 5
+            elif rest.startswith("DF16b", k):
+                toks.append("__bf16")
+                k += 5
+            elif rest[k] in "fd":
+                toks.append("float" if rest[k] == "f" else "double")
+                k += 1
+            else:
+                m = re.match(r"Li(\d+)E", rest[k:])
+                if not m:
+                    break
+                toks.append(m.group(1))
+                k += m.end()
+        args = "<" + ", ".join(toks) + ">"
+    return "::".join(comps) + args
+
+
 def short_name(name: str) -> str:
     base = name.split("(")[0]
     if base.startswith("void "):
         base = base[5:]
+    if base.startswith("_ZN"):
+        return _itanium_short(base)
     return base
 
 
