@@ -28,6 +28,7 @@ struct lbm_ctx {
     std::vector<int32_t> g_node, g_corner;  // corner: [NC][ng]
     std::vector<double> g_w;                // [NC][ng]
     std::vector<uint8_t> g_mask;
+    std::vector<int32_t> fluid;             // fluid node ids, ascending
     int64_t n_solid = 0;
     size_t need = 0;
     char* base = nullptr;
@@ -336,6 +337,11 @@ int lbm_set_geometry(lbm_ctx* c, const lbm_solid* solids, int32_t count) {
     off += align256((size_t)ng * NC * 4);               // g_corner
     off += align256((size_t)ng * NC * fs);              // g_w
     off += align256((size_t)ng);                        // g_mask
+    c->fluid.clear();
+    c->fluid.reserve((size_t)(n - c->n_solid));
+    for (int64_t id = 0; id < n; id++)
+        if (!(c->flags[id] & FLAG_SOLID)) c->fluid.push_back((int32_t)id);
+    off += align256(c->fluid.size() * 4);               // fluid list
     off += 4 * align256((size_t)c->S * 8);              // aux
     off += align256((size_t)REDUCE_BLOCKS * 8 * 8);     // partial
     off += align256(8 * 8);                             // result
@@ -381,15 +387,23 @@ int lbm_bind(lbm_ctx* c, void* dev, size_t bytes, void* stream) {
     d.g_corner = (int32_t*)p; p += align256((size_t)ng * NC * 4);
     d.g_w = p; p += align256((size_t)ng * NC * fs);
     d.g_mask = (uint8_t*)p; p += align256((size_t)ng);
+    d.fluid = (int32_t*)p; p += align256(c->fluid.size() * 4);
     d.aux = (double*)p; p += 4 * align256((size_t)c->S * 8);
     d.partial = (double*)p; p += align256((size_t)REDUCE_BLOCKS * 8 * 8);
     d.result = (double*)p; p += align256(8 * 8);
     d.nonfinite = (int64_t*)p; p += align256((size_t)(REDUCE_BLOCKS + 1) * 8);
     d.n_ghost = (int32_t)ng;
     d.fused = (c->P.options & LBM_OPT_FUSED) ? 1 : 0;
+    d.n_fluid = (int64_t)c->fluid.size();
+    // Fluid-list launches (opt-in: on a 60 %-solid packing they measured
+    // slower than the dense grid, whose rows keep the loads coalesced).
+    d.list = (c->P.options & LBM_OPT_FLUID_LIST) ? 1 : 0;
     // Upload the geometry.
     hipStream_t st = c->stream;
     HIPCHK(c, hipMemcpyAsync(d.flags, c->flags.data(), (size_t)c->n, hipMemcpyHostToDevice, st), "upload flags");
+    if (d.n_fluid > 0)
+        HIPCHK(c, hipMemcpyAsync(d.fluid, c->fluid.data(), (size_t)d.n_fluid * 4, hipMemcpyHostToDevice, st),
+               "upload fluid list");
     if (ng > 0) {
         HIPCHK(c, hipMemcpyAsync(d.g_node, c->g_node.data(), (size_t)ng * 4, hipMemcpyHostToDevice, st), "upload ghosts");
         HIPCHK(c, hipMemcpyAsync(d.g_corner, c->g_corner.data(), (size_t)ng * NC * 4, hipMemcpyHostToDevice, st),

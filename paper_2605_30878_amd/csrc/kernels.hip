@@ -510,14 +510,23 @@ __global__ __launch_bounds__(256) void k_colour_compact(const SN* __restrict__ N
 }
 
 // Colour field of D3Q19 boxes in z-marching tiles: a workgroup owns a
-// CTX x CTY column of nodes and walks up a chunk of planes, keeping the
+// CTX x CTY (64 x 8) column of nodes and walks up a chunk of planes, keeping the
 // compact record (phi_prev, G, p) and flags of three planes of the tile and
 // a one-node ring in LDS.  Every record is fetched from memory once per
 // workgroup (plus the ring and two prologue planes) instead of once per
 // reading node (18 neighbours, 3 to 4 values each); N is read straight into
 // registers before the plane's barrier.  Per node the arithmetic is the row
 // kernel's: the same compact_term in the same order.
-constexpr int CTX = 64, CTY = 4;                  // tile
+#ifndef LBM_CTX
+#define LBM_CTX 64
+#endif
+#ifndef LBM_CTY
+#define LBM_CTY 8
+#endif
+#ifndef LBM_CT_BLOCKS
+#define LBM_CT_BLOCKS 2048
+#endif
+constexpr int CTX = LBM_CTX, CTY = LBM_CTY;        // tile
 constexpr int CRX = CTX + 2, CRY = CTY + 2;       // tile + ring
 
 template <class T>
@@ -825,6 +834,40 @@ __global__ __launch_bounds__(LBM_COLLIDE_BX) void k_collide_stream(const SN* __r
     RowIdx r;
     if (!row_index_sched(rs, P.nx, r)) return;
     collide_node<L, T, SN>(Nsrc, Ndst, Gdst, phi, flags, P, r.ix, r.iy, r.iz);
+}
+
+// Fluid-list forms of the two row kernels: one thread per fluid node of an
+// ascending id list, so no lane idles on a solid node (packings); the
+// per-node functions are the same.
+__device__ __forceinline__ void list_coords(int32_t id, int nx, int ny, int& ix, int& iy, int& iz) {
+    const uint32_t u = (uint32_t)id, a = u / (uint32_t)nx;
+    ix = (int)(u - a * (uint32_t)nx);
+    iy = (int)(a % (uint32_t)ny);
+    iz = (int)(a / (uint32_t)ny);
+}
+
+template <class L, class T, class SN>
+__global__ __launch_bounds__(256) void k_colour_list(const int32_t* __restrict__ list, int64_t n_list,
+                                                     const SN* __restrict__ N, const T* __restrict__ phi_prev,
+                                                     const T* __restrict__ G, const uint8_t* __restrict__ flags,
+                                                     T* __restrict__ phi, KParams<T, L::Q> P) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_list) return;
+    int ix, iy, iz;
+    list_coords(list[k], P.nx, P.ny, ix, iy, iz);
+    colour_compact_node<L, T, SN>(N, phi_prev, G, flags, phi, P, ix, iy, iz);
+}
+
+template <class L, class T, class SN>
+__global__ __launch_bounds__(256) void k_collide_list(const int32_t* __restrict__ list, int64_t n_list,
+                                                      const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
+                                                      T* __restrict__ Gdst, const T* __restrict__ phi,
+                                                      const uint8_t* __restrict__ flags, KParams<T, L::Q> P) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_list) return;
+    int ix, iy, iz;
+    list_coords(list[k], P.nx, P.ny, ix, iy, iz);
+    collide_node<L, T, SN>(Nsrc, Ndst, Gdst, phi, flags, P, ix, iy, iz);
 }
 
 // Macroscopic fields (u, p) of every node into FP64 planes; solids get 0.
@@ -1407,10 +1450,10 @@ static inline bool colour_tile_ok(const StepParams& p) {
     return LBM_COLOUR_TILE && p.nz > 1 && p.nx % CTX == 0 && p.ny % CTY == 0;
 }
 
-// z-chunk: about 2048 workgroups, at least 4 planes each.
+// z-chunk: about LBM_CT_BLOCKS (2048) workgroups, at least 4 planes each.
 static inline int colour_tile_chunk(const StepParams& p) {
     const int64_t cols = (int64_t)(p.nx / CTX) * (p.ny / CTY);
-    int64_t zc = (p.nz * cols + 2047) / 2048;
+    int64_t zc = (p.nz * cols + LBM_CT_BLOCKS - 1) / LBM_CT_BLOCKS;
     if (zc < 4) zc = 4;
     if (zc > p.nz) zc = p.nz;
     return (int)zc;
@@ -1478,6 +1521,13 @@ static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int
                                (const T*)d.B, work, d.flags, p.n, p.S);
         } else {
             const KParams<T, L::Q> kp = make_kparams<T, L, SN>(p);
+            if (d.list) {
+                if (d.n_fluid > 0)
+                    hipLaunchKernelGGL((k_colour_list<L, T, SN>), dim3(blocks_for(d.n_fluid, 256)), dim3(256), 0, st,
+                                       d.fluid, d.n_fluid, (const SN*)d.N[cur], (const T*)d.phi[ps],
+                                       (const T*)d.G[cur], d.flags, work, kp);
+                return hipGetLastError();
+            }
             if constexpr (L::D == 3) {
                 if (colour_tile_ok(p)) {
                     const int zc = colour_tile_chunk(p);
@@ -1501,6 +1551,13 @@ static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int
         }
     } else {
         const KParams<T, L::Q> kp = make_kparams<T, L, SN>(p);
+        if (d.list) {
+            if (d.n_fluid > 0)
+                hipLaunchKernelGGL((k_collide_list<L, T, SN>), dim3(blocks_for(d.n_fluid, 256)), dim3(256), 0, st,
+                                   d.fluid, d.n_fluid, (const SN*)d.N[cur], (SN*)d.N[1 - cur], (T*)d.G[1 - cur],
+                                   (const T*)work, d.flags, kp);
+            return hipGetLastError();
+        }
         const RowSched rs = row_sched(p, bx);
         hipLaunchKernelGGL((k_collide_stream<L, T, SN>), row_grid1(rs, p), dim3(bx), 0, st, (const SN*)d.N[cur],
                            (SN*)d.N[1 - cur], (T*)d.G[1 - cur], (const T*)work, d.flags, kp, rs);

@@ -45,6 +45,9 @@ struct DevState {
     double* result;     // [8] reduced diagnostics
     int64_t* nonfinite; // [REDUCE_BLOCKS + 1]
     int32_t fused;      // 1: D3Q19 steps use the fused one-launch form where the box allows it (opt-in)
+    int32_t* fluid;     // [n_fluid] fluid node ids, ascending
+    int64_t n_fluid;
+    int32_t list;       // 1: colour and collide launch one thread per listed fluid node
 };
 
 constexpr int REDUCE_BLOCKS = 1024;

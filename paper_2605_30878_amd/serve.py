@@ -14,6 +14,7 @@ from __future__ import annotations
 
 import dataclasses
 import math
+import sys
 import time
 from typing import Dict, List, Optional, Sequence
 
@@ -48,14 +49,15 @@ class Result:
 
 
 def mixed_requests(count: int, seed: int = 0, step_scale: float = 1.0, size_scale: float = 1.0,
-                   precision: int = W.FP32, d3q19_fraction: float = 0.4) -> List[Request]:
+                   precision: int = W.FP32, d3q19_fraction: float = 0.4, probe: int = 0) -> List[Request]:
     """The served mix: 60 % D2Q9 boxes with side log-uniform in [64, 512] and
     40 % D3Q19 boxes with side log-uniform in [48, 192] (periodic), a disk or
     ball of radius U(0.2, 0.35) of the side at 0.35 of the box height, a drop
     of radius max(R/2, 10) on its top, contact angle U(20, 160) degrees,
     density ratio log-uniform in [1, 1000] (rho_g = 1), viscosity ratio
     max(1, ratio/10) (mu_g = 0.1), steps U(2000, 20000).  `step_scale` and
-    `size_scale` shrink steps and sides for quick runs."""
+    `size_scale` shrink steps and sides for quick runs; `probe` = 1 sets the
+    fluid-only probe interpolation of the ghost rule for every request."""
     rng = np.random.default_rng(seed)
     reqs = []
     for k in range(count):
@@ -81,7 +83,7 @@ def mixed_requests(count: int, seed: int = 0, step_scale: float = 1.0, size_scal
             shape = (L, L, 1)
         wl = W.Workload(name=f"req{k}", lattice=W.D3Q19 if d3 else W.D2Q9, shape=shape, rho_l=ratio, rho_g=1.0,
                         mu_l=0.1 * mu_ratio, mu_g=0.1, sigma=0.01, W=4.0, mobility=0.02, theta=theta,
-                        solids=solids, liquid=liquid, precision=precision, steps=steps)
+                        solids=solids, liquid=liquid, precision=precision, steps=steps, probe=probe)
         reqs.append(Request(k, wl, steps))
     return reqs
 
@@ -98,7 +100,7 @@ def poisson_arrivals(reqs: Sequence[Request], rate: float, seed: int = 1) -> Lis
 
 class Server:
     def __init__(self, hbm_budget: float = 64e9, max_slots: int = 256, tick_steps: int = 200,
-                 device: str = "cuda:0", keep_state: bool = False):
+                 device: str = "cuda:0", keep_state: bool = False, progress_s: float = 0.0):
         import torch
 
         self.torch = torch
@@ -107,6 +109,7 @@ class Server:
         self.max_slots = int(max_slots)
         self.tick = int(tick_steps)
         self.keep_state = keep_state
+        self.progress_s = float(progress_s)   # > 0: a progress line on stderr this often
         self.stream = torch.cuda.current_stream(self.device)
         self.init_stream = torch.cuda.Stream(device=self.device)
         self.batch = lbm.Batch(max_jobs=max_slots, device=device, stream=self.stream)
@@ -121,8 +124,13 @@ class Server:
         t0 = time.monotonic()
         i = 0
         busy = False
+        last_report = 0.0
         while i < len(pending) or waiting or resident:
             now = time.monotonic() - t0
+            if self.progress_s > 0 and now - last_report >= self.progress_s:
+                last_report = now
+                print(f"[serve] t={now:.0f}s done={len(results)} resident={len(resident)} "
+                      f"waiting={len(waiting)} pending={len(pending) - i}", file=sys.stderr, flush=True)
             while i < len(pending) and pending[i].arrival <= now:
                 waiting.append(pending[i])
                 i += 1
@@ -192,11 +200,13 @@ def summarize(results: Sequence[Result], wall: float) -> Dict[str, float]:
 
 
 def serve_mix(count: int = 64, step_scale: float = 0.1, size_scale: float = 1.0, precision: int = W.FP32,
-              load: float = 0.9, tick_steps: int = 200, seed: int = 0, hbm_budget: float = 64e9) -> Dict[str, object]:
+              load: float = 0.9, tick_steps: int = 200, seed: int = 0, hbm_budget: float = 64e9,
+              probe: int = 0, progress_s: float = 0.0) -> Dict[str, object]:
     """Closed-loop capacity run (all requests at t = 0), then an open-loop run
     with Poisson arrivals at `load` x that capacity; returns both summaries."""
-    reqs = mixed_requests(count, seed=seed, step_scale=step_scale, size_scale=size_scale, precision=precision)
-    srv = Server(hbm_budget=hbm_budget, tick_steps=tick_steps)
+    reqs = mixed_requests(count, seed=seed, step_scale=step_scale, size_scale=size_scale, precision=precision,
+                          probe=probe)
+    srv = Server(hbm_budget=hbm_budget, tick_steps=tick_steps, progress_s=progress_s)
     t0 = time.monotonic()
     res = srv.run(reqs)
     closed = summarize(res, time.monotonic() - t0)
@@ -208,3 +218,24 @@ def serve_mix(count: int = 64, step_scale: float = 0.1, size_scale: float = 1.0,
     return {"closed_loop": closed, "open_loop": opened, "arrival_rate_jobs_s": rate, "requests": count,
             "step_scale": step_scale, "precision": W.PRECISION_NAMES[precision],
             "nonfinite_jobs": sum(1 for r in res if r.obs["nonfinite"] != 0)}
+
+
+def main():
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser(description="served mix: closed-loop capacity, then open-loop latency")
+    ap.add_argument("--count", type=int, default=256)
+    ap.add_argument("--step-scale", type=float, default=1.0)
+    ap.add_argument("--precision", choices=["f32", "f16ofs"], default="f32")
+    ap.add_argument("--probe", type=int, default=0, help="1: fluid-only probe interpolation for every request")
+    ap.add_argument("--seed", type=int, default=0)
+    args = ap.parse_args()
+    prec = W.FP32 if args.precision == "f32" else W.FP16_OFS
+    out = serve_mix(count=args.count, step_scale=args.step_scale, precision=prec, seed=args.seed, probe=args.probe,
+                    progress_s=30.0)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -58,12 +58,13 @@ def test_reduced_precision_contact_angle_against_oracle():
         pytest.skip("no oracle reference yet")
     from paper_2605_30878_amd import lbm
 
-    thetas = sorted(float(t) for t in gold)
+    keys = sorted(gold, key=lambda k: (gold[k].get("theta", float(k.split("/")[0])), k))
     precs = [W.FP32, W.FP16_OFS, W.BF16_OFS]
-    cases = [(t, p) for t in thetas for p in precs]
-    steps = int(gold[str(thetas[0])]["steps"])
+    cases = [(k, p) for k in keys for p in precs]
+    steps = int(gold[keys[0]]["steps"])
     print(f"[angle] cases={cases} steps={steps}", flush=True)
-    wls = [W.sphere_d3q19(64, theta=t, precision=p, steps=steps) for t, p in cases]
+    wls = [W.sphere_d3q19(64, theta=gold[k].get("theta", float(k.split("/")[0])), precision=p,
+                          steps=steps).with_(probe=int(gold[k].get("probe", 0))) for k, p in cases]
     sims = [lbm.Simulation(wl, W.initial_phi(wl)) for wl in wls]
     batch = lbm.Batch(max_jobs=len(sims))
     for _ in range(steps // 2000):
@@ -71,7 +72,7 @@ def test_reduced_precision_contact_angle_against_oracle():
     batch.close()
     worst = {}
     for (t, p), wl, sim in zip(cases, wls, sims):
-        g = gold[str(t)]
+        g = gold[t]
         m = _measure(lbm, sim, wl)
         d_theta = m["theta_apex"] - g["theta_apex"]
         r_speed = m["max_speed"] / g["max_speed"] - 1.0
