@@ -92,7 +92,7 @@ def main() -> int:
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "the library runs one lattice on one GPU; --gpus must be 1 (multi-GPU sharding is not built)",
                           "requested_gpus": args.gpus}), flush=True)
         return 2
 

@@ -180,8 +180,11 @@ int lbm_bind(lbm_ctx* ctx, void* device_ptr, size_t bytes, void* hip_stream);
 int lbm_set_wetting(lbm_ctx* ctx, double theta_deg);
 
 /* Write a field from the host (`count` doubles, see the field list).
- * LBM_FIELD_PHI starts a run (step counter 0); LBM_FIELD_N / _B /
- * _SOLID_PHI overwrite raw state (restore).  Synchronises the stream. */
+ * LBM_FIELD_PHI starts a run (step counter 0); LBM_FIELD_N / _N_OFFSET /
+ * _B / _SOLID_PHI overwrite raw state (restore; _N_OFFSET is exact in every
+ * precision, _N rounds N_i - chi_i once).  Errors: LBM_ESTATE before
+ * LBM_FIELD_PHI (for the raw fields), LBM_EINVAL for a wrong count, a
+ * non-finite initial phi or a read-only field.  Synchronises the stream. */
 int lbm_set_field(lbm_ctx* ctx, int field, const double* host_src, size_t count);
 
 /* Enqueue nsteps >= 0 time steps on the bound stream; returns at once. */
