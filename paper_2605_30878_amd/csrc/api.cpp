@@ -37,6 +37,7 @@ struct lbm_ctx {
     int cur = 0;   // population / compact-record buffer holding the state
     int ps = 0;    // phi buffer holding the solid values of the state
     int from_planes = 1;  // liquid state in the B plane buffer (initial state, restore)
+    bool g_stale = false; // G planes of the record left unwritten by the last steps
     int64_t step = 0;
     std::string err;
 };
@@ -87,6 +88,15 @@ int lbm_lattice(uint32_t lattice, int32_t* c_out, int32_t* q_out) {
         for (int a = 0; a < 3; a++) c_out[i * 3 + a] = c[i][a];
     *q_out = Q;
     return LBM_OK;
+}
+
+// Re-form the G planes of the compact record where the last single-run
+// steps left them unwritten, before a kernel that reads them.
+static hipError_t ensure_g(lbm_ctx* c) {
+    if (!c->g_stale) return hipSuccess;
+    c->g_stale = false;
+    if (c->from_planes) return hipSuccess;
+    return launch_g_record((int)c->P.lattice, c->P.precision, c->d, c->sp, c->cur, c->ps, c->stream);
 }
 
 int lbm_create(const lbm_params* P, lbm_ctx** out) {
@@ -473,6 +483,7 @@ int lbm_set_field(lbm_ctx* c, int field, const double* src, size_t count) {
         HIPCHK(c, launch_init(lat, prec, c->d, c->sp, c->cur, c->ps, c->stream), "init");
         HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
         c->from_planes = 1;
+        c->g_stale = false;
         c->step = 0;
         c->started = true;
         return LBM_OK;
@@ -484,6 +495,7 @@ int lbm_set_field(lbm_ctx* c, int field, const double* src, size_t count) {
         if (!c->from_planes) {
             // The compact liquid record depends on N: write B out to the
             // plane buffer first so that it keeps its value.
+            HIPCHK(c, ensure_g(c), "G record");
             for (int i = 0; i < c->Q; i++) {
                 HIPCHK(c, launch_plane_out(lat, prec, c->d, c->sp, 1, i, c->cur, c->ps, 0, c->stream), "B out");
                 HIPCHK(c, launch_plane_in(lat, prec, c->d, c->sp, 1, i, c->cur, c->stream), "B in");
@@ -513,10 +525,12 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
     if (!c) return LBM_EINVAL;
     if (!c->started) return fail(c, LBM_ESTATE, "set PHI before stepping");
     if (nsteps < 0) return fail(c, LBM_EINVAL, "nsteps must be >= 0");
+    const bool leaves_g = steps_leave_g((int)c->P.lattice, c->d, c->sp);
     for (int64_t k = 0; k < nsteps; k++) {
         hipError_t e = launch_step((int)c->P.lattice, c->P.precision, c->d, c->sp, c->cur, c->ps, c->from_planes,
                                    c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "step launch");
+        if (leaves_g) c->g_stale = true;
         c->cur ^= 1;
         c->ps ^= 1;
         c->from_planes = 0;
@@ -545,6 +559,7 @@ int lbm_step_profiled(lbm_ctx* c, int64_t nsteps, double* ms_out) {
             if (e == hipSuccess) e = hipEventRecord(E[ph + 1], c->stream);
         }
         if (e != hipSuccess) { rc = hip_fail(c, e, "profiled step"); break; }
+        if (steps_leave_g((int)c->P.lattice, c->d, c->sp)) c->g_stale = true;
         c->cur ^= 1;
         c->ps ^= 1;
         c->from_planes = 0;
@@ -651,6 +666,7 @@ int lbm_read_field(lbm_ctx* c, int field, double* dst, size_t count) {
     case LBM_FIELD_N_OFFSET:
     case LBM_FIELD_B:
         if (count != (size_t)c->Q * n) return fail(c, LBM_EINVAL, "N/B have Q*n values");
+        if (field == LBM_FIELD_B) HIPCHK(c, ensure_g(c), "G record");
         for (int i = 0; i < c->Q; i++) {
             HIPCHK(c, launch_plane_out(lat, prec, c->d, c->sp, n_plane_kind(field), i, c->cur, c->ps,
                                        c->from_planes, c->stream),
@@ -710,6 +726,15 @@ int lbm_batch_step(lbm_batch* b, lbm_ctx* const* ctxs, const int64_t* steps, int
         for (int32_t k = 0; k < j; k++)
             if (ctxs[k] == ctxs[j]) return bfail(b, LBM_EINVAL, "a context appears twice");
     }
+    // Runs whose last single-run steps left the G planes of their record
+    // unwritten get them re-formed first (the batched colour kernel reads them).
+    for (int32_t j = 0; j < count; j++) {
+        lbm_ctx* c = ctxs[j];
+        if (!c->g_stale || steps[j] == 0) continue;
+        hipError_t eg = ensure_g(c);
+        if (eg == hipSuccess && c->stream != b->stream) eg = hipStreamSynchronize(c->stream);
+        if (eg != hipSuccess) return bfail(b, LBM_EHIP, std::string("G record: ") + hipGetErrorString(eg));
+    }
     // The staging buffers of the previous call must have reached the device.
     hipError_t e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return bfail(b, LBM_EHIP, std::string("sync: ") + hipGetErrorString(e));
@@ -758,6 +783,7 @@ int lbm_batch_step(lbm_batch* b, lbm_ctx* const* ctxs, const int64_t* steps, int
                     c->ps ^= 1;
                 }
                 c->from_planes = 0;
+                c->g_stale = false;   // the batched collide writes the whole record
                 c->step += n;
             }
         }

@@ -159,6 +159,45 @@ struct GRec {
     static constexpr int P = L::D;   // plane index of p
 };
 
+// Isotropic colour gradient grad = 3 sum_i w_i c_i phi_i, summed over
+// opposite pairs: 3 sum_pairs w_i c_i (phi_i - phi_opp).  Shared by the
+// collision (macro stage) and the colour kernel that re-forms G.
+template <class L, class T>
+__device__ __forceinline__ void grad_stencil(const T (&ph)[L::Q], T& gx, T& gy, T& gz) {
+    gx = gy = gz = T(0);
+    static_for<1, L::Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if constexpr (i < L::opp[i]) {
+            constexpr int j = L::opp[i];
+            constexpr T wi = T(L::w[i]);
+            const T d = wi * (ph[i] - ph[j]);
+            if constexpr (L::c[i][0] != 0) gx += cmul<L::c[i][0]>(d);
+            if constexpr (L::c[i][1] != 0) gy += cmul<L::c[i][1]>(d);
+            if constexpr (L::c[i][2] != 0) gz += cmul<L::c[i][2]>(d);
+        }
+    });
+    gx *= T(3);
+    gy *= T(3);
+    gz *= T(3);
+}
+
+// Recolouring vector of Eq. A12, G = (2/W) max(phi (1 - phi), 0) n_phi:
+// the normal where |grad phi| is resolved, the amplitude clamped at 0 where
+// phi leaves [0, 1].
+template <class T>
+__device__ __forceinline__ void recolour_vector(T phi, T gx, T gy, T gz, T inv_W, T n_thresh2, T (&G)[3]) {
+    const T gn2 = gx * gx + gy * gy + gz * gz;
+    T amp = phi * (T(1) - phi);
+    amp = amp > T(0) ? amp : T(0);
+    G[0] = G[1] = G[2] = T(0);
+    if (gn2 > n_thresh2) {
+        const T k = T(2) * inv_W * amp / sqrt(gn2);
+        G[0] = k * gx;
+        G[1] = k * gy;
+        G[2] = k * gz;
+    }
+}
+
 // Node output of the macroscopic stage.
 template <class T>
 struct Macro {
@@ -181,24 +220,19 @@ __device__ __forceinline__ void macro_stage(const T (&N)[L::Q], const T (&ph)[L:
     const T phi = ph[0];
     m.phi = phi;
     // Isotropic stencils, summed over opposite pairs (i, opp i):
-    // grad = 3 sum w c phi = 3 sum_pairs w c_i (phi_i - phi_opp),
+    // grad = 3 sum w c phi (grad_stencil),
     // lap = 6 sum_{i>0} w (phi_i - phi) = 6 (sum_pairs w (phi_i + phi_opp) - (1 - w0) phi).
-    T gx = 0, gy = 0, gz = 0, lap = 0;
+    T gx, gy, gz;
+    grad_stencil<L, T>(ph, gx, gy, gz);
+    T lap = 0;
     static_for<1, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         if constexpr (i < L::opp[i]) {
             constexpr int j = L::opp[i];
             constexpr T wi = T(L::w[i]);
-            const T d = wi * (ph[i] - ph[j]);
-            if constexpr (L::c[i][0] != 0) gx += cmul<L::c[i][0]>(d);
-            if constexpr (L::c[i][1] != 0) gy += cmul<L::c[i][1]>(d);
-            if constexpr (L::c[i][2] != 0) gz += cmul<L::c[i][2]>(d);
             lap += wi * (ph[i] + ph[j]);
         }
     });
-    gx *= T(3);
-    gy *= T(3);
-    gz *= T(3);
     lap = T(6) * (lap - (T(1) - w0) * phi);
     m.grad[0] = gx;
     m.grad[1] = gy;
@@ -331,19 +365,7 @@ __device__ __forceinline__ void collide_stage(const Macro<T>& m, const T (&Pi)[6
             Ns[j] = sym - asym;
         }
     });
-    // Recolouring vector: normal where |grad phi| is resolved, amplitude
-    // clamped at 0 where phi leaves [0, 1].
-    const T gx = m.grad[0], gy = m.grad[1], gz = m.grad[2];
-    const T gn2 = gx * gx + gy * gy + gz * gz;
-    T amp = m.phi * (T(1) - m.phi);
-    amp = amp > T(0) ? amp : T(0);
-    G[0] = G[1] = G[2] = T(0);
-    if (gn2 > P.n_thresh2) {
-        const T k = T(2) * P.inv_W * amp / sqrt(gn2);
-        G[0] = k * gx;
-        G[1] = k * gy;
-        G[2] = k * gz;
-    }
+    recolour_vector<T>(m.phi, m.grad[0], m.grad[1], m.grad[2], P.inv_W, P.n_thresh2, G);
 }
 
 // Neighbour index tables of a node: nb[i] = index of x + c_i (periodic).
@@ -715,6 +737,167 @@ __global__ __launch_bounds__(CTX * CTY) void k_colour_tile(const SN* __restrict_
     }
 }
 
+// The tiled colour kernel with G re-formed in LDS (the collide then writes
+// only p of the record): G(y) = (2/W) max(phi(1-phi), 0) grad phi/|grad phi|
+// from the same phi_prev field and the same stencil the collision used, so
+// it equals the stored G bit for bit.  LDS per workgroup: phi_prev of four
+// planes on the tile and a two-node ring, and G, p, flags of three planes on
+// the tile and a one-node ring.  It saves 24 B per node of HBM traffic
+// (FP32) but forms G for the ring too and needs a third barrier per plane:
+// measured slower at 256^3 (FP32 17.5k against 17.7k MLUPS, FP16 23.0k
+// against 25.6k), so it is built only with LBM_G_RECOMPUTE=1.
+#ifndef LBM_G_RECOMPUTE
+#define LBM_G_RECOMPUTE 0
+#endif
+constexpr int CQX = CTX + 4, CQY = CTY + 4;       // tile + two rings
+
+template <class T>
+struct ColourSmemG {
+    T ph[4][CQY][CQX];         // phi_prev, planes by slot4(z)
+    T g[3][3][CRY][CRX];       // G, planes by slot3(z)
+    T p[3][CRY][CRX];
+    uint8_t fl[3][CRY][CRX];
+};
+
+__device__ __forceinline__ int slot4(int z) { return (z % 4 + 4) % 4; }
+
+template <class T>
+__device__ __forceinline__ void colour_g_load_phi(ColourSmemG<T>& sm, int z, int x0, int y0,
+                                                  const T* __restrict__ phi_prev, int nx, int ny, int nz) {
+    const int sl = slot4(z);
+    const int Z = wrapc(z, nz);
+    for (int k = threadIdx.x; k < CQX * CQY; k += CTX * CTY) {
+        const int lx = k % CQX, ly = k / CQX;
+        const int X = wrapc(x0 + lx - 2, nx), Y = wrapc(y0 + ly - 2, ny);
+        sm.ph[sl][ly][lx] = ld(phi_prev, (uint32_t)X + (uint32_t)nx * ((uint32_t)Y + (uint32_t)ny * (uint32_t)Z));
+    }
+}
+
+template <class T>
+__device__ __forceinline__ void colour_g_load_pf(ColourSmemG<T>& sm, int z, int x0, int y0,
+                                                 const T* __restrict__ prec, const uint8_t* __restrict__ flags,
+                                                 int nx, int ny, int nz) {
+    const int sl = slot3(z);
+    const int Z = wrapc(z, nz);
+    for (int k = threadIdx.x; k < CRX * CRY; k += CTX * CTY) {
+        const int lx = k % CRX, ly = k / CRX;
+        const int X = wrapc(x0 + lx - 1, nx), Y = wrapc(y0 + ly - 1, ny);
+        const uint32_t id = (uint32_t)X + (uint32_t)nx * ((uint32_t)Y + (uint32_t)ny * (uint32_t)Z);
+        sm.p[sl][ly][lx] = ld(prec, id);
+        sm.fl[sl][ly][lx] = ld(flags, id);
+    }
+}
+
+// G of plane z on the tile and its ring from phi_prev of planes z-1..z+1.
+template <class T>
+__device__ __forceinline__ void colour_g_form(ColourSmemG<T>& sm, int z, const KParams<T, 19>& P) {
+    using L = LatD3Q19;
+    const int sg = slot3(z);
+    for (int k = threadIdx.x; k < CRX * CRY; k += CTX * CTY) {
+        const int lx = k % CRX, ly = k / CRX;
+        T ph[19];
+        static_for<0, 19>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            ph[i] = sm.ph[slot4(z + L::c[i][2])][ly + 1 + L::c[i][1]][lx + 1 + L::c[i][0]];
+        });
+        T gx, gy, gz, G[3];
+        grad_stencil<L, T>(ph, gx, gy, gz);
+        recolour_vector<T>(ph[0], gx, gy, gz, P.inv_W, P.n_thresh2, G);
+        sm.g[sg][0][ly][lx] = G[0];
+        sm.g[sg][1][ly][lx] = G[1];
+        sm.g[sg][2][ly][lx] = G[2];
+    }
+}
+
+template <class T, class SN>
+__global__ __launch_bounds__(CTX * CTY) void k_colour_tile_g(const SN* __restrict__ N, const T* __restrict__ phi_prev,
+                                                             const T* __restrict__ prec,
+                                                             const uint8_t* __restrict__ flags, T* __restrict__ phi,
+                                                             KParams<T, 19> P, TileSched ts, int zc) {
+    using L = LatD3Q19;
+    __shared__ ColourSmemG<T> sm;
+    int bx, by, bz;
+    tile_index(ts, bx, by, bz);
+    const int x0 = bx * CTX, y0 = by * CTY;
+    const int z0 = bz * zc;
+    const int z1 = min(z0 + zc, P.nz);
+    const int tx = threadIdx.x % CTX, ty = threadIdx.x / CTX;
+    const int64_t S = P.S;
+    const uint32_t xy = (uint32_t)(x0 + tx) + (uint32_t)P.nx * (uint32_t)(y0 + ty);
+    const uint32_t plane = (uint32_t)P.nx * (uint32_t)P.ny;
+    for (int z = z0 - 2; z <= z0 + 1; z++) colour_g_load_phi<T>(sm, z, x0, y0, phi_prev, P.nx, P.ny, P.nz);
+    colour_g_load_pf<T>(sm, z0 - 1, x0, y0, prec, flags, P.nx, P.ny, P.nz);
+    colour_g_load_pf<T>(sm, z0, x0, y0, prec, flags, P.nx, P.ny, P.nz);
+    __syncthreads();
+    colour_g_form<T>(sm, z0 - 1, P);
+    colour_g_form<T>(sm, z0, P);
+    __syncthreads();   // phi_prev of plane z0 - 2 is overwritten next
+    for (int z = z0; z < z1; z++) {
+        // N of plane z; phi_prev of plane z + 2, p and flags of plane z + 1
+        SN raw[19];
+#pragma unroll
+        for (int i = 0; i < 19; i++) raw[i] = ld(N + (int64_t)i * S, xy + plane * (uint32_t)z);
+        colour_g_load_phi<T>(sm, z + 2, x0, y0, phi_prev, P.nx, P.ny, P.nz);
+        colour_g_load_pf<T>(sm, z + 1, x0, y0, prec, flags, P.nx, P.ny, P.nz);
+        __syncthreads();
+        colour_g_form<T>(sm, z + 1, P);
+        __syncthreads();
+        const int s0 = slot3(z), sx = tx + 1, sy = ty + 1;
+        const uint8_t f = sm.fl[s0][sy][sx];
+        if (!(f & FLAG_SOLID)) {
+            const bool near = (f & FLAG_NEAR_SOLID) != 0;
+            T acc = 0;
+            static_for<0, L::Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+                const T n = NStore<T, SN>::dec(raw[i], P.n_s);
+                if constexpr (i == 0) {
+                    acc += sm.ph[slot4(z)][sy + 1][sx + 1] * (P.chi[0] + n);
+                } else {
+                    int zs = z - cz, qx = sx - cx, qy = sy - cy;
+                    T sgn = T(1);
+                    if (near && (sm.fl[slot3(zs)][qy][qx] & FLAG_SOLID)) {
+                        zs = z;
+                        qx = sx;
+                        qy = sy;
+                        sgn = T(-1);
+                    }
+                    const int sl = slot3(zs);
+                    const T gx = cx != 0 ? sm.g[sl][0][qy][qx] : T(0);
+                    const T gy = cy != 0 ? sm.g[sl][1][qy][qx] : T(0);
+                    const T gz = cz != 0 ? sm.g[sl][2][qy][qx] : T(0);
+                    acc += compact_term<L, T, i>(n, sm.ph[slot4(zs)][qy + 1][qx + 1], gx, gy, gz, sm.p[sl][qy][qx],
+                                                 sgn, P);
+                }
+            });
+            st(phi, xy + plane * (uint32_t)z, acc);
+        }
+        __syncthreads();
+    }
+}
+
+// G planes of the record re-formed from phi_prev at every fluid node (for
+// the row, batched and read-out kernels after steps that left them
+// unwritten).
+template <class L, class T>
+__global__ __launch_bounds__(256) void k_g_record(const T* __restrict__ phi_prev, const uint8_t* __restrict__ flags,
+                                                  T* __restrict__ G, KParams<T, L::Q> P) {
+    RowIdx r;
+    if (!row_index(P.nx, P.ny, r)) return;
+    const uint32_t x = (uint32_t)r.x;
+    if (ld(flags, x) & FLAG_SOLID) return;
+    uint32_t nb[L::Q];
+    neighbours<L>(r.ix, r.iy, r.iz, P.nx, P.ny, P.nz, nb);
+    T ph[L::Q];
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) ph[i] = ld(phi_prev, nb[i]);
+    T gx, gy, gz, Gv[3];
+    grad_stencil<L, T>(ph, gx, gy, gz);
+    recolour_vector<T>(ph[0], gx, gy, gz, P.inv_W, P.n_thresh2, Gv);
+#pragma unroll
+    for (int a = 0; a < L::D; a++) st(G + (int64_t)a * P.S, x, Gv[a]);
+}
+
 // One direction plane of B from the compact record into FP64 (read-out).
 template <class L, class T, class SN>
 __global__ __launch_bounds__(256) void k_compact_B_plane(const SN* __restrict__ N, const T* __restrict__ phi_prev,
@@ -778,7 +961,7 @@ __global__ __launch_bounds__(256) void k_ghost(const int32_t* __restrict__ g_nod
 // Fused stencil + forces + collision + recolouring + push streaming with
 // halfway bounce-back, one node.  Writes the streamed N* and the node's
 // compact liquid record (G, p).
-template <class L, class T, class SN>
+template <class L, class T, class SN, bool WG = true>
 __device__ __forceinline__ void collide_node(const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
                                              T* __restrict__ Gdst, const T* __restrict__ phi,
                                              const uint8_t* __restrict__ flags, const KParams<T, L::Q>& P, int ix,
@@ -820,20 +1003,23 @@ __device__ __forceinline__ void collide_node(const SN* __restrict__ Nsrc, SN* __
 #pragma unroll
         for (int i = 0; i < Q; i++) st(Ndst + (int64_t)i * S, nb[i], e[i]);
     }
+    if constexpr (WG) {
 #pragma unroll
-    for (int a = 0; a < L::D; a++) st(Gdst + (int64_t)a * S, x, G[a]);
+        for (int a = 0; a < L::D; a++) st(Gdst + (int64_t)a * S, x, G[a]);
+    }
     st(Gdst + (int64_t)GRec<L>::P * S, x, m.p);
 }
 
-// One thread per node of an x-row; grid (x-blocks, ny, nz).
-template <class L, class T, class SN>
+// One thread per node of an x-row.  WG = false leaves the G planes of the
+// record unwritten (the tiled colour kernel re-forms G from phi).
+template <class L, class T, class SN, bool WG = true>
 __global__ __launch_bounds__(LBM_COLLIDE_BX) void k_collide_stream(const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
                                                                    T* __restrict__ Gdst, const T* __restrict__ phi,
                                                                    const uint8_t* __restrict__ flags,
                                                                    KParams<T, L::Q> P, RowSched rs) {
     RowIdx r;
     if (!row_index_sched(rs, P.nx, r)) return;
-    collide_node<L, T, SN>(Nsrc, Ndst, Gdst, phi, flags, P, r.ix, r.iy, r.iz);
+    collide_node<L, T, SN, WG>(Nsrc, Ndst, Gdst, phi, flags, P, r.ix, r.iy, r.iz);
 }
 
 // Fluid-list forms of the two row kernels: one thread per fluid node of an
@@ -1508,6 +1694,14 @@ static hipError_t fused_phase_t(int phase, const DevState& d, const StepParams& 
     }
 }
 
+// Steps whose collide leaves the G planes of the record unwritten: the
+// colour kernel of the next step re-forms G in LDS (D3Q19 tiled boxes on the
+// dense-grid, two-launch path).
+template <class L>
+static inline bool g_mode(const DevState& d, const StepParams& p) {
+    return LBM_G_RECOMPUTE && L::D == 3 && !d.list && !d.fused && colour_tile_ok(p);
+}
+
 template <class L, class T, class SN>
 static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int cur, int ps, int from_planes,
                           hipStream_t st, bool allow_fused = true) {
@@ -1533,9 +1727,15 @@ static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int
                     const int zc = colour_tile_chunk(p);
                     const TileSched ts = tile_sched(p);
                     const unsigned nb = (unsigned)(ts.xt * ts.yt * ((p.nz + zc - 1) / zc));
-                    hipLaunchKernelGGL((k_colour_tile<T, SN>), dim3(nb), dim3(CTX * CTY), 0, st,
-                                       (const SN*)d.N[cur], (const T*)d.phi[ps], (const T*)d.G[cur], d.flags, work,
-                                       kp, ts, zc);
+                    if (g_mode<L>(d, p)) {
+                        hipLaunchKernelGGL((k_colour_tile_g<T, SN>), dim3(nb), dim3(CTX * CTY), 0, st,
+                                           (const SN*)d.N[cur], (const T*)d.phi[ps],
+                                           (const T*)d.G[cur] + (int64_t)GRec<L>::P * p.S, d.flags, work, kp, ts, zc);
+                    } else {
+                        hipLaunchKernelGGL((k_colour_tile<T, SN>), dim3(nb), dim3(CTX * CTY), 0, st,
+                                           (const SN*)d.N[cur], (const T*)d.phi[ps], (const T*)d.G[cur], d.flags,
+                                           work, kp, ts, zc);
+                    }
                     return hipGetLastError();
                 }
             }
@@ -1559,8 +1759,15 @@ static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int
             return hipGetLastError();
         }
         const RowSched rs = row_sched(p, bx);
-        hipLaunchKernelGGL((k_collide_stream<L, T, SN>), row_grid1(rs, p), dim3(bx), 0, st, (const SN*)d.N[cur],
-                           (SN*)d.N[1 - cur], (T*)d.G[1 - cur], (const T*)work, d.flags, kp, rs);
+        if (g_mode<L>(d, p)) {
+            hipLaunchKernelGGL((k_collide_stream<L, T, SN, false>), row_grid1(rs, p), dim3(bx), 0, st,
+                               (const SN*)d.N[cur], (SN*)d.N[1 - cur], (T*)d.G[1 - cur], (const T*)work, d.flags, kp,
+                               rs);
+        } else {
+            hipLaunchKernelGGL((k_collide_stream<L, T, SN, true>), row_grid1(rs, p), dim3(bx), 0, st,
+                               (const SN*)d.N[cur], (SN*)d.N[1 - cur], (T*)d.G[1 - cur], (const T*)work, d.flags, kp,
+                               rs);
+        }
     }
     return hipGetLastError();
 }
@@ -1706,6 +1913,22 @@ hipError_t launch_plane_out(int lattice, uint32_t prec, const DevState& d, const
 hipError_t launch_plane_in(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int which, int dir,
                            int cur, hipStream_t st) {
     LBM_DISPATCH(plane_in_t, d, p, which, dir, cur, st);
+}
+
+template <class L, class T, class SN>
+static hipError_t g_record_t(const DevState& d, const StepParams& p, int cur, int ps, hipStream_t st) {
+    const KParams<T, L::Q> kp = make_kparams<T, L, SN>(p);
+    const int bx = row_block(p.nx);
+    hipLaunchKernelGGL((k_g_record<L, T>), row_grid(p, bx), dim3(bx), 0, st, (const T*)d.phi[ps], d.flags,
+                       (T*)d.G[cur], kp);
+    return hipGetLastError();
+}
+hipError_t launch_g_record(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
+                           hipStream_t st) {
+    LBM_DISPATCH(g_record_t, d, p, cur, ps, st);
+}
+bool steps_leave_g(int lattice, const DevState& d, const StepParams& p) {
+    return lattice == 1 ? g_mode<LatD3Q19>(d, p) : g_mode<LatD2Q9>(d, p);
 }
 // Per job: the descriptor and two block offsets; per group: alignment slack.
 static size_t batch_job_bytes() { return sizeof(BJob<LatD3Q19, double, double>) + 2 * sizeof(int64_t); }

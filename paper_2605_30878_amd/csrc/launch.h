@@ -86,6 +86,14 @@ hipError_t launch_plane_out(int lattice, uint32_t prec, const DevState& d, const
                             int dir, int cur, int ps, int from_planes, hipStream_t stream);
 // One plane from FP64 aux[0].  which: 0 = N plane `dir`, 1 = B plane `dir`
 // of the plane buffer, 2 = solid entries of both phi buffers.
+// G planes of the compact record of buffer `cur` re-formed from phi[ps].
+hipError_t launch_g_record(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
+                           hipStream_t stream);
+// True when single-run steps leave the G planes of the record unwritten
+// (the tiled colour kernel re-forms them); row, batched and read-out
+// kernels then need launch_g_record first.
+bool steps_leave_g(int lattice, const DevState& d, const StepParams& p);
+
 hipError_t launch_plane_in(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int which,
                            int dir, int cur, hipStream_t stream);
 

@@ -267,13 +267,15 @@ def test_observe_and_mass():
         assert abs(o1["momentum"][a] - oo["momentum"][a]) <= 1e-12 * scale
 
 
-@pytest.mark.parametrize("prec", [W.FP64, W.FP32, W.FP16_OFS], ids=["f64", "f32", "fp16ofs"])
-def test_restore_roundtrip_is_bitwise(prec):
+@pytest.mark.parametrize("prec,n", [(W.FP64, 32), (W.FP32, 32), (W.FP16_OFS, 32), (W.FP32, 64), (W.FP16_OFS, 64)],
+                         ids=["f64", "f32", "fp16ofs", "f32_tiled", "fp16ofs_tiled"])
+def test_restore_roundtrip_is_bitwise(prec, n):
     """Raw state (populations as stored offsets, liquid populations, solid
     phi) read out and written into a fresh context continues bit-identically
-    (checkpoint / resume)."""
+    (checkpoint / resume).  At 64^3 the steps run the tiled colour kernel
+    that re-forms G, so the read-out first rebuilds G."""
     lbm = _lbm()
-    wl = W.sphere_d3q19(32, theta=120.0, precision=prec)
+    wl = W.sphere_d3q19(n, theta=120.0, precision=prec)
     phi0 = W.initial_phi(wl)
     a = lbm.Simulation(wl, phi0)
     a.step(25)
