@@ -549,12 +549,21 @@ __global__ __launch_bounds__(256) void k_colour_compact(const SN* __restrict__ N
 #define LBM_CT_BLOCKS 2048
 #endif
 constexpr int CTX = LBM_CTX, CTY = LBM_CTY;        // tile
+// Record planes held in LDS: 3 (load one plane ahead, two barriers per
+// plane) or 5 (load two planes ahead, one barrier per plane; 69 KB of LDS
+// in FP32, measured slightly slower: 401 against 395 us at 256^3).
+#ifndef LBM_COLOUR_SLOTS
+#define LBM_COLOUR_SLOTS 3
+#endif
+constexpr int CSL = LBM_COLOUR_SLOTS;
+static_assert(CSL == 3 || CSL == 5, "three or five record planes");
+__device__ __forceinline__ int slotc(int z) { return (z % CSL + CSL) % CSL; }
 constexpr int CRX = CTX + 2, CRY = CTY + 2;       // tile + ring
 
 template <class T>
 struct ColourSmem {
-    T rec[3][5][CRY][CRX];     // phi_prev, Gx, Gy, Gz, p; planes by slot3(z)
-    uint8_t fl[3][CRY][CRX];
+    T rec[CSL][5][CRY][CRX];   // phi_prev, Gx, Gy, Gz, p; planes by slotc(z)
+    uint8_t fl[CSL][CRY][CRX];
 };
 
 __device__ __forceinline__ int wrapc(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
@@ -584,10 +593,12 @@ __device__ __forceinline__ void tile_index(const TileSched& s, int& bx, int& by,
 }
 
 // LBM_COLOUR_PIPE=1 issues the loads of the next plane before the current
-// plane's arithmetic; it needs ~50 more VGPRs and measured no faster.
+// plane's arithmetic; it needs ~50 more VGPRs (two waves per SIMD fewer) and
+// measured slower at 256^3 (FP32 446 against 395 us, FP16 419 against 282).
 #ifndef LBM_COLOUR_PIPE
 #define LBM_COLOUR_PIPE 0
 #endif
+static_assert(!LBM_COLOUR_PIPE || CSL == 3, "the pipelined form keeps three record planes");
 
 // The record and flags of plane z for the tile and its ring, staged through
 // registers: each thread fetches up to two of the CRX * CRY entries (one
@@ -627,7 +638,7 @@ __device__ __forceinline__ void colour_tile_load(ColourSmem<T>& sm, int z, int x
                                                  const T* __restrict__ phi_prev, const T* __restrict__ G,
                                                  const uint8_t* __restrict__ flags, int nx, int ny, int nz,
                                                  int64_t S) {
-    const int sl = slot3(z);
+    const int sl = slotc(z);
     const int Z = wrapc(z, nz);
     for (int k = threadIdx.x; k < CRX * CRY; k += CTX * CTY) {
         const int lx = k % CRX, ly = k / CRX;
@@ -644,7 +655,7 @@ __device__ __forceinline__ void colour_tile_load(ColourSmem<T>& sm, int z, int x
 
 template <class T>
 __device__ __forceinline__ void colour_tile_store(ColourSmem<T>& sm, const TileRec<T>& r, int z) {
-    const int sl = slot3(z);
+    const int sl = slotc(z);
 #pragma unroll
     for (int e = 0; e < 2; e++) {
         const int k = threadIdx.x + e * CTX * CTY;
@@ -673,8 +684,9 @@ __global__ __launch_bounds__(CTX * CTY) void k_colour_tile(const SN* __restrict_
     const int64_t S = P.S;
     const uint32_t xy = (uint32_t)(x0 + tx) + (uint32_t)P.nx * (uint32_t)(y0 + ty);
     const uint32_t plane = (uint32_t)P.nx * (uint32_t)P.ny;
-    colour_tile_load<T>(sm, z0 - 1, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
-    colour_tile_load<T>(sm, z0, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
+    constexpr int AHEAD = (CSL - 1) / 2;   // planes loaded ahead of the one computed
+    for (int zz = z0 - 1; zz < z0 + AHEAD; zz++)
+        colour_tile_load<T>(sm, zz, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
     SN raw[19];
 #if LBM_COLOUR_PIPE
     TileRec<T> rec;
@@ -695,13 +707,13 @@ __global__ __launch_bounds__(CTX * CTY) void k_colour_tile(const SN* __restrict_
         }
         colour_tile_fetch<T>(rec, z + 2, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
 #else
-        // N of plane z, the record of plane z + 1 into LDS
+        // N of plane z, the record of plane z + AHEAD into LDS
 #pragma unroll
         for (int i = 0; i < 19; i++) raw[i] = ld(N + (int64_t)i * S, xy + plane * (uint32_t)z);
-        colour_tile_load<T>(sm, z + 1, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
+        colour_tile_load<T>(sm, z + AHEAD, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
         __syncthreads();
 #endif
-        const int s0 = slot3(z), sx = tx + 1, sy = ty + 1;
+        const int s0 = slotc(z), sx = tx + 1, sy = ty + 1;
         const uint8_t f = sm.fl[s0][sy][sx];
         if (!(f & FLAG_SOLID)) {
             const bool near = (f & FLAG_NEAR_SOLID) != 0;
@@ -713,7 +725,7 @@ __global__ __launch_bounds__(CTX * CTY) void k_colour_tile(const SN* __restrict_
                 if constexpr (i == 0) {
                     acc += sm.rec[s0][0][sy][sx] * (P.chi[0] + n);
                 } else {
-                    int sl = slot3(z - cz), qx = sx - cx, qy = sy - cy;
+                    int sl = slotc(z - cz), qx = sx - cx, qy = sy - cy;
                     T sgn = T(1);
                     if (near && (sm.fl[sl][qy][qx] & FLAG_SOLID)) {
                         sl = s0;
@@ -729,7 +741,9 @@ __global__ __launch_bounds__(CTX * CTY) void k_colour_tile(const SN* __restrict_
             });
             st(phi, xy + plane * (uint32_t)z, acc);
         }
-        __syncthreads();
+        // With three slots the next load overwrites a plane this one read;
+        // with five, the next iteration's barrier already orders them.
+        if (CSL == 3 || LBM_COLOUR_PIPE) __syncthreads();
 #if LBM_COLOUR_PIPE
 #pragma unroll
         for (int i = 0; i < 19; i++) raw[i] = nxt[i];
