@@ -59,6 +59,9 @@ def _itanium_short(base: str) -> str:
             elif rest[k] in "fd":
                 toks.append("float" if rest[k] == "f" else "double")
                 k += 1
+            elif rest.startswith("Lb1E", k) or rest.startswith("Lb0E", k):
+                toks.append("true" if rest[k + 2] == "1" else "false")
+                k += 4
             else:
                 m = re.match(r"Li(\d+)E", rest[k:])
                 if not m:
