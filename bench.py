@@ -178,6 +178,7 @@ def main() -> int:
                     "n_fluid": n_fluid, "n_ghost": obs1["n_ghost"],
                     "porosity_nodes": round(n_fluid / wl.nodes, 4),
                     "ghost_probe": "fluid corners" if wl.probe else "all corners",
+                    "dead_end_fill": bool(wl.fill),
                     "mflups": round(n_fluid * args.steps / (dt * 1e6), 2)}),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

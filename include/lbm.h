@@ -69,10 +69,14 @@ enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_OFS = 2, LBM_BF16_OFS = 3 };
  * x_F = x_G + n_s (text before Eq. 8) interpolates all 2^D corners, solid
  * ones with their current value (ghosts: last step's; deeper solid nodes:
  * (1 + cos theta)/2).  With LBM_OPT_FLUID_PROBE only the fluid corners take
- * part, their weights rescaled to sum 1; a probe with no fluid corner keeps
- * all corners.  In narrow gaps between solids (packings) the default lets
- * probes read the far solid's (1 + cos theta)/2 and, below 90 degrees at
- * density ratio 10, drives gas nodes there unstable within ~200 steps. */
+ * part, their weights rescaled to sum 1.  A probe with no fluid corner (a
+ * ghost in the gap between touching solids, its normal pointing into the
+ * other solid) takes the ghost's fluid lattice neighbours instead, weighted
+ * by w_i and rescaled to sum 1 (the axis neighbours alone if there are more
+ * than 2^D; lbm_set_geometry returns LBM_EINVAL if none of them is on an
+ * axis).  In narrow gaps between solids (packings) the default lets probes
+ * read the far solid's (1 + cos theta)/2 and, below 90 degrees at density
+ * ratio 10, drives gas nodes there unstable within ~200 steps. */
 #define LBM_OPT_FLUID_PROBE 2
 
 /* Launch shape of the colour and collide kernels.  By default they launch
@@ -90,6 +94,17 @@ enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_OFS = 2, LBM_BF16_OFS = 3 };
  * (4e4 to 1.4e6 nodes) the replays measured 3 to 13 % slower than direct
  * launches, the per-kernel cost being on the device, not in the launch. */
 #define LBM_OPT_GRAPH 8
+
+/* Geometry conditioning for packings (not in the paper, whose solids are
+ * single convex bodies).  With LBM_OPT_FILL_DEAD_ENDS, lbm_set_geometry makes
+ * solid every fluid node that has at most one fluid lattice neighbour, and
+ * repeats on the new solid set until no such node is left.  Such nodes sit in
+ * the contacts between touching solids, narrower than a node; left fluid,
+ * they are wedged between the two solids' ghost values and, below 90 degrees,
+ * grow a velocity that doubles every few hundred steps.  A filled node that
+ * borders the fluid is a ghost node whose normal n_s points to the one fluid
+ * neighbour it keeps. */
+#define LBM_OPT_FILL_DEAD_ENDS 16
 
 /* Ghost-node rule: Eq. 9 (this paper) or Eq. 10 (Fakhari et al.). */
 enum { LBM_GHOST_EQ9 = 0, LBM_GHOST_FAKHARI = 1 };
@@ -127,7 +142,8 @@ typedef struct {
     int32_t options;        /* bit 0 (LBM_OPT_FUSED): use the fused one-launch D3Q19 step where it applies;
                                bit 1 (LBM_OPT_FLUID_PROBE): fluid-only probe interpolation;
                                bit 2 (LBM_OPT_FLUID_LIST): fluid-list launches;
-                               bit 3 (LBM_OPT_GRAPH): captured two-step graphs in lbm_step */
+                               bit 3 (LBM_OPT_GRAPH): captured two-step graphs in lbm_step;
+                               bit 4 (LBM_OPT_FILL_DEAD_ENDS): dead-end fluid nodes made solid */
     double rho_l, rho_g;    /* liquid (phi = 1) and gas (phi = 0) densities, > 0 */
     double mu_l, mu_g;      /* dynamic viscosities, > 0 */
     double sigma;           /* surface tension, >= 0 */
@@ -172,7 +188,10 @@ int lbm_create(const lbm_params* params, lbm_ctx** out);
  * a fluid lattice neighbour, Section 1), and build the ghost list: analytic
  * normal n_s, probe point x_F = x_G + n_s and its 2^D interpolation corners
  * and weights (Section 2, text before Eq. 8).  `solids` is read only during
- * the call.  May be called once, before lbm_bind. */
+ * the call.  May be called once, before lbm_bind.  Errors: LBM_ESTATE when
+ * called again; LBM_EINVAL for a bad list, an unknown kind, a ball wider than
+ * the box, a zero half-space normal, or (LBM_OPT_FLUID_PROBE) a ghost whose
+ * probe fallback has no axis neighbour to use; LBM_ENOMEM on host memory. */
 int lbm_set_geometry(lbm_ctx* ctx, const lbm_solid* solids, int32_t count);
 
 /* Bytes of device memory lbm_bind needs (known after lbm_set_geometry). */

@@ -41,7 +41,7 @@ class _Params(C.Structure):
                 ("rho_l", C.c_double), ("rho_g", C.c_double), ("mu_l", C.c_double), ("mu_g", C.c_double),
                 ("sigma", C.c_double), ("W", C.c_double), ("mobility", C.c_double),
                 ("g", C.c_double * 3), ("theta_deg", C.c_double), ("ghost_rule", C.c_int32),
-                ("probe", C.c_int32)]
+                ("probe", C.c_int32), ("fill", C.c_int32)]
 
 
 class _Solid(C.Structure):
@@ -126,6 +126,7 @@ class OracleSim:
         P.theta_deg = wl.theta
         P.ghost_rule = int(wl.ghost_rule)
         P.probe = int(getattr(wl, "probe", 0))
+        P.fill = int(getattr(wl, "fill", 0))
         ns = len(wl.solids)
         arr = (_Solid * max(ns, 1))()
         for k, s in enumerate(wl.solids):

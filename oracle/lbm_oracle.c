@@ -56,7 +56,10 @@ typedef struct {
     int32_t ghost_rule;   /* 0 = Eq. 9, 1 = Eq. 10 (Fakhari et al.) */
     int32_t probe;        /* corners of the probe interpolation: 0 = all eight
                              (solid ones from the snapshot), 1 = fluid ones
-                             only, weights rescaled to sum 1 */
+                             only, weights rescaled to sum 1 (no fluid
+                             corner: the ghost's fluid lattice neighbours) */
+    int32_t fill;         /* 1: fluid nodes with at most one fluid lattice
+                             neighbour become solid, pass after pass */
 } orc_params;
 
 typedef struct {
@@ -525,6 +528,42 @@ void* orc_create(const orc_params* P, const orc_solid* solids, int nsolids,
             break;
         }
     }
+    /* READING (dead-end fill, option): a fluid node joined to the rest of
+     * the fluid by at most one lattice link (a pocket in the contact between
+     * two solids, narrower than a node) is made solid; passes repeat on the
+     * new solid set until no such node is left.  A filled node belongs to no
+     * primitive: its normal is the direction of the one fluid neighbour it
+     * keeps at the end (none: it is interior and needs no normal). */
+    if (P->fill == 1) {
+        uint8_t* mark = (uint8_t*)calloc(n, 1);
+        if (!mark) FAIL("out of memory");
+        for (;;) {
+            long changed = 0;
+            for (long id = 0; id < n; id++) {
+                mark[id] = 0;
+                if (s->solid[id]) continue;
+                int nf = 0;
+                for (int i = 1; i < Q; i++)
+                    if (!s->solid[neighbour(s, id, s->L.c[i])]) nf++;
+                if (nf <= 1) { mark[id] = 1; changed++; }
+            }
+            if (changed == 0) break;
+            for (long id = 0; id < n; id++)
+                if (mark[id]) { s->solid[id] = 2; }
+        }
+        free(mark);
+        for (long id = 0; id < n; id++) {
+            if (s->solid[id] != 2) continue;
+            s->solid[id] = 1;
+            for (int a = 0; a < 3; a++) s->nrm[id * 3 + a] = 0.0;
+            for (int i = 1; i < Q; i++) {
+                if (s->solid[neighbour(s, id, s->L.c[i])]) continue;
+                double len = sqrt((double)(s->L.c[i][0] * s->L.c[i][0] + s->L.c[i][1] * s->L.c[i][1] +
+                                           s->L.c[i][2] * s->L.c[i][2]));
+                for (int a = 0; a < 3; a++) s->nrm[id * 3 + a] = s->L.c[i][a] / len;
+            }
+        }
+    }
     /* Ghost nodes: solid nodes with at least one fluid neighbour (Section 1). */
     long ng = 0;
     for (long id = 0; id < n; id++) {
@@ -563,15 +602,46 @@ void* orc_create(const orc_params* P, const orc_solid* solids, int nsolids,
         }
         /* READING (alternative probe, option): phi_F is meant to be the fluid's
          * colour at x_F (the text before Eq. 8 places x_F in the fluid), so
-         * only fluid corners take part, their weights rescaled to sum to 1;
-         * a probe with no fluid corner keeps all corners. */
+         * only fluid corners take part, their weights rescaled to sum to 1.
+         * Where x_F has no fluid corner (a ghost in the gap between two
+         * touching solids, whose normal points into the other solid), phi_F
+         * is taken from the ghost's own fluid lattice neighbours instead,
+         * weighted by w_i and rescaled to sum to 1: all of them when there
+         * are at most nc, else the axis (face) neighbours alone. */
         if (P->probe == 1) {
             double wf = 0.0;
             for (int k = 0; k < nc; k++)
                 if (!s->solid[s->corner[ng * 8 + k]]) wf += s->cw[ng * 8 + k];
-            if (wf > 0.0)
+            if (wf > 0.0) {
                 for (int k = 0; k < nc; k++)
                     s->cw[ng * 8 + k] = s->solid[s->corner[ng * 8 + k]] ? 0.0 : s->cw[ng * 8 + k] / wf;
+            } else {
+                long nb[QMAX];
+                double wn[QMAX];
+                int axis[QMAX], nf = 0, naxis = 0;
+                for (int i = 1; i < Q; i++) {
+                    long y = neighbour(s, id, s->L.c[i]);
+                    if (s->solid[y]) continue;
+                    nb[nf] = y;
+                    wn[nf] = s->L.w[i];
+                    axis[nf] = abs(s->L.c[i][0]) + abs(s->L.c[i][1]) + abs(s->L.c[i][2]) == 1;
+                    naxis += axis[nf];
+                    nf++;
+                }
+                const int axis_only = nf > nc;
+                if (axis_only && naxis == 0) FAIL("ghost with no fluid probe corner and too many diagonal fluid neighbours");
+                double wsum = 0.0;
+                int k = 0;
+                for (int j = 0; j < nf; j++) {
+                    if (axis_only && !axis[j]) continue;
+                    s->corner[ng * 8 + k] = nb[j];
+                    s->cw[ng * 8 + k] = wn[j];
+                    wsum += wn[j];
+                    k++;
+                }
+                for (int j = 0; j < k; j++) s->cw[ng * 8 + j] /= wsum;
+                for (; k < nc; k++) { s->corner[ng * 8 + k] = nb[0]; s->cw[ng * 8 + k] = 0.0; }
+            }
         }
         s->ghost[ng++] = id;
     }

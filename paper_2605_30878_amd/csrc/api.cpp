@@ -283,9 +283,32 @@ int lbm_set_geometry(lbm_ctx* c, const lbm_solid* solids, int32_t count) {
                     }
         }
     }
+    if (c->P.options & LBM_OPT_FILL_DEAD_ENDS) {
+        // Fluid nodes joined to the other fluid nodes by at most one lattice
+        // link become solid (owner -2), pass after pass until none is left.
+        std::vector<int64_t> dead;
+        for (;;) {
+            dead.clear();
+            for (int64_t z = 0; z < nz; z++)
+                for (int64_t y = 0; y < ny; y++)
+                    for (int64_t x = 0; x < nx; x++) {
+                        const int64_t id = id_of(x, y, z);
+                        if (owner[id] != -1) continue;
+                        int open = 0;
+                        for (int i = 1; i < Q && open < 2; i++) {
+                            const int64_t nb = id_of(wrapi(x + cv[i][0], nx), wrapi(y + cv[i][1], ny),
+                                                     D == 3 ? wrapi(z + cv[i][2], nz) : 0);
+                            open += owner[nb] == -1 ? 1 : 0;
+                        }
+                        if (open < 2) dead.push_back(id);
+                    }
+            if (dead.empty()) break;
+            for (int64_t id : dead) owner[id] = -2;
+        }
+    }
     int64_t nsolid = 0;
     for (int64_t id = 0; id < n; id++)
-        if (owner[id] >= 0) { c->flags[id] = FLAG_SOLID; nsolid++; }
+        if (owner[id] != -1) { c->flags[id] = FLAG_SOLID; nsolid++; }
     c->n_solid = nsolid;
     // Node classes from the lattice stencil.
     std::vector<int64_t> ghosts;
@@ -317,10 +340,18 @@ int lbm_set_geometry(lbm_ctx* c, const lbm_solid* solids, int32_t count) {
     for (int64_t g = 0; g < ng; g++) {
         const int64_t id = ghosts[g];
         const int64_t x = id % nx, y = (id / nx) % ny, z = id / ((int64_t)nx * ny);
-        const lbm_solid& s = solids[owner[id]];
-        // Solid normal n_s pointing out of the solid (Eq. 7).
+        // Solid normal n_s pointing out of the solid (Eq. 7).  A filled
+        // dead-end node has one fluid neighbour left: n_s points to it.
         double nv[3] = {0, 0, 0};
-        if (s.kind == 0) {
+        if (owner[id] == -2) {
+            for (int i = 1; i < Q; i++) {
+                const int64_t nb = id_of(wrapi(x + cv[i][0], nx), wrapi(y + cv[i][1], ny),
+                                         D == 3 ? wrapi(z + cv[i][2], nz) : 0);
+                if (!(c->flags[nb] & FLAG_SOLID))
+                    for (int a = 0; a < 3; a++) nv[a] = cv[i][a];
+            }
+        } else if (solids[owner[id]].kind == 0) {
+            const lbm_solid& s = solids[owner[id]];
             const int dims[3] = {nx, ny, nz};
             const double pos[3] = {(double)x, (double)y, (double)z};
             for (int a = 0; a < D; a++) {
@@ -330,7 +361,7 @@ int lbm_set_geometry(lbm_ctx* c, const lbm_solid* solids, int32_t count) {
                 nv[a] = dd;
             }
         } else {
-            for (int a = 0; a < D; a++) nv[a] = s.normal[a];
+            for (int a = 0; a < D; a++) nv[a] = solids[owner[id]].normal[a];
         }
         double len = std::sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
         if (len > 0) {
@@ -361,16 +392,54 @@ int lbm_set_geometry(lbm_ctx* c, const lbm_solid* solids, int32_t count) {
             if (c->flags[cid] & FLAG_SOLID) mask |= (uint8_t)(1u << k);
         }
         if (c->P.options & LBM_OPT_FLUID_PROBE) {
-            // phi_F from the fluid corners only, weights rescaled to sum 1
-            // (a probe with no fluid corner keeps all eight).
+            // phi_F from the fluid corners only, weights rescaled to sum 1.
             double wf = 0.0;
             for (int k = 0; k < NC; k++)
                 if (!((mask >> k) & 1u)) wf += c->g_w[(size_t)k * ng + g];
-            if (wf > 0.0)
+            if (wf > 0.0) {
                 for (int k = 0; k < NC; k++) {
-                    double& w = c->g_w[(size_t)k * ng + g];
-                    w = ((mask >> k) & 1u) ? 0.0 : w / wf;
+                    double& wk = c->g_w[(size_t)k * ng + g];
+                    wk = ((mask >> k) & 1u) ? 0.0 : wk / wf;
                 }
+            } else {
+                // The probe cell lies wholly in solid (a ghost in the gap
+                // between touching solids): phi_F from the ghost's fluid
+                // lattice neighbours, weighted by w_i and rescaled to sum 1;
+                // the axis neighbours alone when there are more than NC.
+                int64_t nb_id[32];
+                double nb_w[32];
+                bool nb_axis[32];
+                int nf = 0, naxis = 0;
+                for (int i = 1; i < Q; i++) {
+                    const int64_t nb = id_of(wrapi(x + cv[i][0], nx), wrapi(y + cv[i][1], ny),
+                                             D == 3 ? wrapi(z + cv[i][2], nz) : 0);
+                    if (c->flags[nb] & FLAG_SOLID) continue;
+                    nb_id[nf] = nb;
+                    nb_w[nf] = w[i];
+                    nb_axis[nf] = std::abs(cv[i][0]) + std::abs(cv[i][1]) + std::abs(cv[i][2]) == 1;
+                    naxis += nb_axis[nf] ? 1 : 0;
+                    nf++;
+                }
+                const bool axis_only = nf > NC;
+                if (axis_only && naxis == 0)
+                    return fail(c, LBM_EINVAL, "ghost node whose probe has no fluid corner and more diagonal "
+                                                "fluid neighbours than interpolation slots");
+                int k = 0;
+                double sum = 0.0;
+                for (int j = 0; j < nf; j++) {
+                    if (axis_only && !nb_axis[j]) continue;
+                    c->g_corner[(size_t)k * ng + g] = (int32_t)nb_id[j];
+                    c->g_w[(size_t)k * ng + g] = nb_w[j];
+                    sum += nb_w[j];
+                    k++;
+                }
+                for (int j = 0; j < k; j++) c->g_w[(size_t)j * ng + g] /= sum;
+                for (; k < NC; k++) {
+                    c->g_corner[(size_t)k * ng + g] = (int32_t)nb_id[0];
+                    c->g_w[(size_t)k * ng + g] = 0.0;
+                }
+                mask = 0;   // every slot now names a fluid node
+            }
         }
         c->g_node[g] = (int32_t)id;
         c->g_mask[g] = mask;

@@ -21,6 +21,9 @@ ABI_VERSION = 1
 OK, EINVAL, ESTATE, ENOMEM, EHIP, EUNSTABLE = 0, -1, -2, -3, -4, -5
 OPT_FUSED = 1
 OPT_FLUID_PROBE = 2
+OPT_FLUID_LIST = 4
+OPT_GRAPH = 8
+OPT_FILL_DEAD_ENDS = 16
 FIELD_PHI, FIELD_N, FIELD_B, FIELD_U, FIELD_P, FIELD_SOLID_PHI, FIELD_FLAGS, FIELD_N_OFFSET = range(8)
 FLAG_SOLID, FLAG_NEAR_SOLID, FLAG_GHOST = 1, 2, 4
 
@@ -111,7 +114,8 @@ def lattice(lat: int) -> np.ndarray:
 
 def make_params(wl: W.Workload, options: int = 0) -> lbm_params:
     p = lbm_params()
-    p.options = int(options) | (OPT_FLUID_PROBE if getattr(wl, "probe", 0) else 0)
+    p.options = (int(options) | (OPT_FLUID_PROBE if getattr(wl, "probe", 0) else 0)
+                 | (OPT_FILL_DEAD_ENDS if getattr(wl, "fill", 0) else 0))
     p.abi_version = ABI_VERSION
     p.lattice = int(wl.lattice)
     p.precision = int(wl.precision)

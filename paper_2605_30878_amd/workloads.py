@@ -79,6 +79,7 @@ class Workload:
     steps: int = 1000
     ghost_rule: int = 0
     probe: int = 0   # 0: probe interpolation over all corners; 1: fluid corners only
+    fill: int = 0    # 1: fluid nodes with at most one fluid lattice neighbour become solid (repeated)
 
     @property
     def nodes(self) -> int:
@@ -202,7 +203,7 @@ def plate_d2q9(nx: int, ny: int, theta: float, drop_radius: float, W: float = 4.
 
 def porous_d3q19(n: int = 384, sphere_radius: float = 12.0, porosity: float = 0.40,
                  seed: int = 0, precision: int = FP32, front: Optional[float] = None,
-                 max_iter: int = 20000, probe: int = 1) -> Workload:
+                 max_iter: int = 20000, probe: int = 1, fill: int = 1) -> Workload:
     """Dynamic contact line in a random packing of non-overlapping spheres.
 
     Sphere count is chosen so that the continuous solid fraction equals
@@ -210,10 +211,15 @@ def porous_d3q19(n: int = 384, sphere_radius: float = 12.0, porosity: float = 0.
     periodic minimum image until no pair overlaps.  The wetting liquid
     (theta = 45 deg) fills x < front with tanh interfaces at x = front and
     x = 0; rho_l/rho_g = 10, mu_l/mu_g = 10, body acceleration (1e-6, 0, 0).
-    The ghost-rule probe interpolates fluid corners only (probe = 1): with
-    all corners, probes in the gaps between touching spheres read the far
-    solid's (1 + cos theta)/2 and the run diverges within a few hundred steps
-    (oracle and library alike)."""
+    The ghost-rule probe interpolates fluid corners only (probe = 1), and a
+    ghost whose probe cell has no fluid corner takes its fluid lattice
+    neighbours: with all corners, probes in the gaps between touching spheres
+    read the far solid's (1 + cos theta)/2 and the run diverges within a few
+    hundred steps (oracle and library alike).  Fluid nodes joined to the
+    pore space by at most one lattice link (fill = 1; 0.03 % of the pore
+    nodes at 384^3, in the contacts between spheres) are made solid: left
+    fluid, such a node between the two spheres' ghost values is driven
+    unstable below 90 degrees."""
     centres = sphere_packing(n, sphere_radius, 1.0 - porosity, seed, max_iter)
     solids = [Solid(0, tuple(float(v) for v in c), sphere_radius) for c in centres]
     front = n / 4.0 if front is None else front
@@ -222,7 +228,7 @@ def porous_d3q19(n: int = 384, sphere_radius: float = 12.0, porosity: float = 0.
         rho_l=10.0, rho_g=1.0, mu_l=1.0, mu_g=0.1, sigma=0.01, W=4.0, mobility=0.02,
         g=(1e-6, 0.0, 0.0), theta=45.0, solids=solids,
         liquid=[LiquidRegion("slab", axis=0, lo=0.0, hi=front, width=4.0)],
-        precision=precision, steps=50000, probe=probe)
+        precision=precision, steps=50000, probe=probe, fill=fill)
 
 
 def sphere_packing(n: int, radius: float, solid_fraction: float, seed: int,

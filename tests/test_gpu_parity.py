@@ -166,17 +166,30 @@ def test_porous_packing_fp64_parity():
     """A seeded packing of non-overlapping spheres (solid fraction 0.6, many
     ghosts, spheres across the periodic edges), wetting liquid in a slab,
     density ratio 10, body force along x."""
-    wl = W.porous_d3q19(n=40, sphere_radius=5.0, porosity=0.40, seed=0, precision=W.FP64, front=10.0, probe=0)
+    wl = W.porous_d3q19(n=40, sphere_radius=5.0, porosity=0.40, seed=0, precision=W.FP64, front=10.0, probe=0,
+                        fill=0)
     wl = wl.with_(g=(1e-5, 0.0, 0.0))
     _run_pair(wl, [1, 30], TOL64)
 
 
-def test_porous_fluid_probe_fp64_parity():
-    """The same packing with the fluid-only probe interpolation (the porous
-    workload's setting), which keeps the wetting (45 degree) run stable:
-    300 steps against the oracle."""
-    wl = W.porous_d3q19(n=40, sphere_radius=5.0, porosity=0.40, seed=0, precision=W.FP64, front=10.0, probe=1)
+@pytest.mark.parametrize("seed", [0, 1])
+def test_porous_fluid_probe_fp64_parity(seed):
+    """The same packing in the porous workload's setting: fluid-only probe
+    interpolation (with the fluid-neighbour fallback for probes wholly in
+    solid) and dead-end nodes filled.  The library's solid set equals the
+    oracle's; 300 steps against the oracle."""
+    wl = W.porous_d3q19(n=40, sphere_radius=5.0, porosity=0.40, seed=seed, precision=W.FP64, front=10.0)
+    assert wl.probe == 1 and wl.fill == 1
     wl = wl.with_(g=(1e-5, 0.0, 0.0))
+    lbm = _lbm()
+    sim = lbm.Simulation(wl, W.initial_phi(wl))
+    solid = (sim.read(lbm.FIELD_FLAGS).astype(np.int64) & lbm.FLAG_SOLID) > 0
+    sim.close()
+    osim = oracle.OracleSim(wl, W.initial_phi(wl))
+    assert np.array_equal(solid, osim.get(oracle.F_SOLID) > 0.5)
+    plain = oracle.OracleSim(wl.with_(fill=0), W.initial_phi(wl))
+    assert (osim.get(oracle.F_SOLID) > plain.get(oracle.F_SOLID)).sum() > 0   # the fill is exercised
+    del osim, plain
     _run_pair(wl, [1, 30, 300], TOL64)
 
 
@@ -187,7 +200,7 @@ def test_fluid_list_launch_fp64_parity():
                     mu_l=10.0, mu_g=0.1, sigma=0.01, W=4.0, theta=60.0,
                     solids=[W.Solid(0, (22.0, 19.0, 12.0), 8.5)],
                     liquid=[W.LiquidRegion("ball", (22.0, 19.0, 21.0), 8.0, width=4.0)])
-    _run_pair(wl, [1, 20, 200], TOL64, options=4)
+    _run_pair(wl, [1, 20, 200], TOL64, options=4)   # LBM_OPT_FLUID_LIST
 
 
 @pytest.mark.parametrize("prec", [W.FP32, W.FP16_OFS], ids=["f32", "fp16ofs"])

@@ -118,25 +118,99 @@ def test_flat_wall_probe_is_a_node():
 def test_fluid_only_probe_weights(wl):
     """The fluid-only probe (option): solid corners get weight 0 and the fluid
     corners keep their bi/trilinear weights in proportion, summing to 1; a
-    probe whose corners are all fluid is unchanged, and one with no fluid
-    corner keeps the plain weights."""
+    probe whose corners are all fluid is unchanged.  A probe with no fluid
+    corner takes the ghost's fluid lattice neighbours (found here by brute
+    force), weighted by w_i and rescaled to sum 1, the axis neighbours alone
+    when there are more than 2^D."""
     a = oracle.OracleSim(wl.with_(probe=0), W.initial_phi(wl))
     b = oracle.OracleSim(wl.with_(probe=1), W.initial_phi(wl))
     ids_a, _, corners, wa = a.ghosts()
     ids_b, _, corners_b, wb = b.ghosts()
-    assert np.array_equal(ids_a, ids_b) and np.array_equal(corners, corners_b)
+    assert np.array_equal(ids_a, ids_b)
     solid = a.get(oracle.F_SOLID) > 0.5
     nc = 2 ** (3 if wl.lattice == W.D3Q19 else 2)
     cs = solid[corners[:, :nc]]
     wa, wb = wa[:, :nc], wb[:, :nc]
+    corners, corners_b = corners[:, :nc], corners_b[:, :nc]
     fluid_w = np.where(cs, 0.0, wa).sum(axis=1)
     has_fluid = fluid_w > 0
+    assert np.array_equal(corners[has_fluid], corners_b[has_fluid])
     assert np.allclose(wb.sum(axis=1), 1.0, atol=1e-15)
     assert np.all(wb[has_fluid][cs[has_fluid]] == 0.0)
     ratio = np.where(cs, 0.0, wa)[has_fluid] / fluid_w[has_fluid, None]
     assert np.allclose(wb[has_fluid], ratio, atol=1e-15)
     all_fluid = ~cs.any(axis=1)
     assert np.array_equal(wb[all_fluid], wa[all_fluid])
-    assert np.array_equal(wb[~has_fluid], wa[~has_fluid])
     # the rescaling is exercised
     assert (has_fluid & ~all_fluid).sum() > 0
+    # the fallback, against a brute-force list of fluid neighbours
+    nx, ny, nz = wl.shape
+    tab = oracle.lattice_tables(wl.lattice)
+    c, wlat = tab["c"], tab["w"]
+    for g in np.flatnonzero(~has_fluid):
+        gid = int(ids_b[g])
+        x, y, z = gid % nx, (gid // nx) % ny, gid // (nx * ny)
+        nb = []
+        for ci, wi in zip(c[1:], wlat[1:]):
+            j = (x + ci[0]) % nx + nx * ((y + ci[1]) % ny + ny * ((z + ci[2]) % nz))
+            if not solid[j]:
+                nb.append((j, wi, int(np.abs(ci).sum()) == 1))
+        assert nb, "a ghost has a fluid neighbour by definition"
+        if len(nb) > nc:
+            nb = [t for t in nb if t[2]]
+        tot = sum(t[1] for t in nb)
+        want = sorted((j, wi / tot) for j, wi, _ in nb)
+        got = sorted((int(k), float(v)) for k, v in zip(corners_b[g], wb[g]) if v > 0)
+        assert [k for k, _ in got] == [k for k, _ in want]
+        assert np.allclose([v for _, v in got], [v for _, v in want], atol=1e-15)
+        assert not solid[corners_b[g]].any()
+    if wl.name.startswith("d3q19_porous"):
+        assert (~has_fluid).sum() > 0, "the packing exercises the fallback"
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_dead_end_fill(seed):
+    """The dead-end fill (option): starting from the plain solid set, fluid
+    nodes with at most one fluid lattice neighbour are made solid, all at
+    once, pass after pass (brute force in numpy); every fluid node left has
+    at least two fluid neighbours, and a filled ghost's normal is the unit
+    vector towards its one remaining fluid neighbour."""
+    wl = W.porous_d3q19(n=40, sphere_radius=5.0, porosity=0.40, seed=seed, precision=W.FP64, front=10.0)
+    assert wl.fill == 1
+    plain = oracle.OracleSim(wl.with_(fill=0), W.initial_phi(wl))
+    filled = oracle.OracleSim(wl, W.initial_phi(wl))
+    shape = tuple(reversed(wl.shape))
+    s0 = (plain.get(oracle.F_SOLID) > 0.5).reshape(shape)
+    s1 = (filled.get(oracle.F_SOLID) > 0.5).reshape(shape)
+    c = _velocities(wl.lattice)
+
+    def fluid_neighbours(solid):
+        cnt = np.zeros(solid.shape, np.int64)
+        for ci in c[1:]:
+            cnt += ~np.roll(solid, shift=(-ci[2], -ci[1], -ci[0]), axis=(0, 1, 2))
+        return cnt
+
+    want = s0.copy()
+    while True:
+        dead = ~want & (fluid_neighbours(want) <= 1)
+        if not dead.any():
+            break
+        want |= dead
+    assert np.array_equal(s1, want)
+    new = s1 & ~s0
+    assert new.sum() > 0
+    assert np.all(fluid_neighbours(s1)[~s1] >= 2)
+    ids, nrm, _, _ = filled.ghosts()
+    nx, ny, nz = wl.shape
+    flat_new = new.reshape(-1)
+    checked = 0
+    for g, gid in enumerate(ids):
+        if not flat_new[gid]:
+            continue
+        x, y, z = gid % nx, (gid // nx) % ny, gid // (nx * ny)
+        open_dirs = [ci for ci in c[1:] if not s1[(z + ci[2]) % nz, (y + ci[1]) % ny, (x + ci[0]) % nx]]
+        assert len(open_dirs) == 1
+        u = np.asarray(open_dirs[0], float)
+        assert np.allclose(nrm[g], u / np.linalg.norm(u), atol=1e-15)
+        checked += 1
+    assert checked > 0
