@@ -85,6 +85,9 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true", help="skip the served-mix latency measurement")
     ap.add_argument("--fused", action="store_true", help="use the fused one-launch D3Q19 step")
+    ap.add_argument("--layout", choices=["box", "sparse"], default=None,
+                    help="device storage: box planes, or fluid-only slots with a neighbour table "
+                         "(default: sparse for the porous packing, box otherwise)")
     ap.add_argument("--full-mix", action="store_true",
                     help="served mix at full size: 256 requests, 2000-20000 steps each")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -115,7 +118,9 @@ def main() -> int:
         wl = W.porous_d3q19(n=384 if args.size == 256 else args.size, precision=prec)
     else:
         wl = W.sphere_d3q19(args.size, theta=args.theta, precision=prec)
-    sim = lbm.Simulation(wl, W.initial_phi(wl), device="cuda:0", options=lbm.OPT_FUSED if args.fused else 0)
+    layout = args.layout or ("sparse" if args.workload == "porous" else "box")
+    options = (lbm.OPT_FUSED if args.fused else 0) | (lbm.OPT_SPARSE if layout == "sparse" else 0)
+    sim = lbm.Simulation(wl, W.initial_phi(wl), device="cuda:0", options=options)
     obs0 = sim.observe()
     sim.step(args.warmup)
     torch.cuda.synchronize()
@@ -140,6 +145,14 @@ def main() -> int:
         alg_bytes = n_fluid * (2 * Q * s_n + 2 * (D + 2) * s_t) + wl.nodes
         impl_bytes = 2 * Q * s_n + 2 * (D + 2) * s_t
         kernel = "k_step_fused"
+    elif layout == "sparse":
+        # the same per fluid node; flags are read per fluid slot, and the
+        # neighbour-slot table ((Q - 1) x 4 bytes per fluid node, read by both
+        # launches) is layout overhead, counted in impl_bytes only
+        alg_bytes = n_fluid * (2 * Q * s_n + s_t + (D + 1) * s_t + 1)
+        impl_bytes = ((Q * s_n + 2 * s_t + (D + 1) * s_t) + (2 * Q * s_n + s_t + (D + 1) * s_t)
+                      + 2 * (Q - 1) * 4)
+        kernel = "k_collide_sparse"
     else:
         # collide-stream launch: N read and N* written (2 Q s_n), phi read
         # once, the record (G, p) written ((D + 1) s_t); one flag byte per node
@@ -149,7 +162,7 @@ def main() -> int:
         kernel = "k_collide_stream"
     k_ms = ms["collide"] / args.steps
     achieved = alg_bytes / (k_ms * 1e-3) / 1e9
-    workload_key = f"d3q19_{args.workload}_{wl.shape[0]}_{args.precision}"
+    workload_key = f"d3q19_{args.workload}_{wl.shape[0]}_{args.precision}" + ("_sparse" if layout == "sparse" else "")
     traffic = measured_traffic(kernel, workload_key)
     # paper-state bytes per lattice update: N and B read once and written once
     step_bytes = 4 * Q * s_n
@@ -171,14 +184,14 @@ def main() -> int:
                     "box": [args.size] * 3, "sphere_radius": 48 * args.size / 256,
                     "drop_radius": 40 * args.size / 256, "rho_ratio": 1000, "mu_ratio": 100,
                     "theta_deg": args.theta, "W": 4.0, "sigma": 0.01, "storage": args.precision,
-                    "n_fluid": n_fluid, "n_ghost": obs1["n_ghost"]} if args.workload == "sphere" else
+                    "n_fluid": n_fluid, "n_ghost": obs1["n_ghost"], "layout": layout} if args.workload == "sphere" else
                    {"workload": f"D3Q19 porous packing {wl.shape[0]}^3", "lattice": "D3Q19",
                     "box": list(wl.shape), "spheres": len(wl.solids), "sphere_radius": 12, "rho_ratio": 10,
                     "mu_ratio": 10, "theta_deg": 45, "body_accel": 1e-6, "storage": args.precision,
                     "n_fluid": n_fluid, "n_ghost": obs1["n_ghost"],
                     "porosity_nodes": round(n_fluid / wl.nodes, 4),
                     "ghost_probe": "fluid corners" if wl.probe else "all corners",
-                    "dead_end_fill": bool(wl.fill),
+                    "dead_end_fill": bool(wl.fill), "layout": layout,
                     "mflups": round(n_fluid * args.steps / (dt * 1e6), 2)}),
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,

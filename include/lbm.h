@@ -106,6 +106,20 @@ enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_OFS = 2, LBM_BF16_OFS = 3 };
  * neighbour it keeps. */
 #define LBM_OPT_FILL_DEAD_ENDS 16
 
+/* Fluid-only storage for mostly solid boxes (packings).  With LBM_OPT_SPARSE
+ * every device plane holds one entry per slot instead of per box node.  The
+ * slots are the fluid nodes in box order, then the ghost nodes in list
+ * order, then one slot that stands for every other solid node.  A table of
+ * Q - 1 slot indices per fluid node (4 (Q - 1) bytes) gives each fluid
+ * node's neighbours.  Launches cover the fluid slots only, and a step
+ * computes the same values as the box layout, bit for bit.  Fields still
+ * cross the ABI in box order.  Restrictions: it excludes LBM_OPT_FUSED and
+ * LBM_OPT_FLUID_LIST (lbm_create returns LBM_EINVAL); such contexts step
+ * only through lbm_step (lbm_batch_step returns LBM_EINVAL); setting
+ * LBM_FIELD_SOLID_PHI needs one value for all non-ghost solid nodes
+ * (LBM_EINVAL otherwise). */
+#define LBM_OPT_SPARSE 32
+
 /* Ghost-node rule: Eq. 9 (this paper) or Eq. 10 (Fakhari et al.). */
 enum { LBM_GHOST_EQ9 = 0, LBM_GHOST_FAKHARI = 1 };
 
@@ -143,7 +157,8 @@ typedef struct {
                                bit 1 (LBM_OPT_FLUID_PROBE): fluid-only probe interpolation;
                                bit 2 (LBM_OPT_FLUID_LIST): fluid-list launches;
                                bit 3 (LBM_OPT_GRAPH): captured two-step graphs in lbm_step;
-                               bit 4 (LBM_OPT_FILL_DEAD_ENDS): dead-end fluid nodes made solid */
+                               bit 4 (LBM_OPT_FILL_DEAD_ENDS): dead-end fluid nodes made solid;
+                               bit 5 (LBM_OPT_SPARSE): fluid-only storage */
     double rho_l, rho_g;    /* liquid (phi = 1) and gas (phi = 0) densities, > 0 */
     double mu_l, mu_g;      /* dynamic viscosities, > 0 */
     double sigma;           /* surface tension, >= 0 */
@@ -259,7 +274,9 @@ int lbm_batch_create(void* device_table, size_t bytes, void* hip_stream, lbm_bat
 
 /* Advance ctxs[j] by steps[j] >= 0 steps (count contexts, each at most
  * once).  Waits for the batch stream's previous work first (the table is
- * reused), then enqueues and returns; results appear like lbm_step's. */
+ * reused), then enqueues and returns; results appear like lbm_step's.
+ * LBM_EINVAL for a null, repeated or LBM_OPT_SPARSE context or a negative
+ * step count; LBM_ESTATE for a context that has not started. */
 int lbm_batch_step(lbm_batch* batch, lbm_ctx* const* ctxs, const int64_t* steps, int32_t count);
 
 /* Release the batch (host memory only). */

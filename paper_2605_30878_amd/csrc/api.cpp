@@ -40,6 +40,15 @@ struct lbm_ctx {
     bool g_stale = false; // G planes of the record left unwritten by the last steps
     hipStream_t cap_stream = nullptr;               // private stream for graph capture
     hipGraphExec_t graph2[2] = {nullptr, nullptr};  // two-step graphs, by buffer parity
+    // Fluid-only layout (LBM_OPT_SPARSE): slots are the fluid nodes, the
+    // ghost nodes, then one slot for every other solid node.
+    bool sparse = false;
+    int64_t M = 0;                     // slots
+    std::vector<int32_t> slot_of;      // [n] slot of each node
+    std::vector<int32_t> node_of;      // [M - 1] node of each fluid / ghost slot
+    std::vector<uint8_t> slot_flags;   // [M]
+    std::vector<uint32_t> nbt;         // [Q - 1][n_fluid] slot of fluid slot k + c_i
+    std::vector<double> stage;         // [M] host staging of one plane
     int64_t step = 0;
     std::string err;
 };
@@ -159,10 +168,13 @@ int lbm_create(const lbm_params* P, lbm_ctx** out) {
     if (!(P->mobility > 0)) return fail(nullptr, LBM_EINVAL, "mobility must be > 0");
     for (int a = 0; a < 3; a++)
         if (!std::isfinite(P->body_accel[a])) return fail(nullptr, LBM_EINVAL, "body_accel not finite");
+    if ((P->options & LBM_OPT_SPARSE) && (P->options & (LBM_OPT_FUSED | LBM_OPT_FLUID_LIST)))
+        return fail(nullptr, LBM_EINVAL, "LBM_OPT_SPARSE excludes LBM_OPT_FUSED and LBM_OPT_FLUID_LIST");
 
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
     if (!c) return fail(nullptr, LBM_ENOMEM, "host allocation failed");
     c->P = *P;
+    c->sparse = (P->options & LBM_OPT_SPARSE) != 0;
     const int(*cv)[3];
     const double* w;
     lattice_table((int)P->lattice, c->D, c->Q, c->NC, &cv, &w);
@@ -444,6 +456,49 @@ int lbm_set_geometry(lbm_ctx* c, const lbm_solid* solids, int32_t count) {
         c->g_node[g] = (int32_t)id;
         c->g_mask[g] = mask;
     }
+    if (c->sparse) {
+        // Slots: fluid nodes in box order, ghost nodes in list order, then
+        // the slot of every other solid node.
+        const int64_t nf = n - nsolid;
+        const int64_t M = nf + ng + 1;
+        if ((uint64_t)((M + 127) / 128 * 128) * std::max(elem_size(c->P.precision), phi_size(c->P.precision)) >
+                0xFFFFFFFFull ||
+            (uint64_t)(Q - 1) * (uint64_t)nf > 0x7FFFFFFFFFFFull)
+            return fail(c, LBM_EINVAL, "sparse layout too large");
+        try {
+            c->slot_of.assign((size_t)n, (int32_t)(M - 1));
+            c->node_of.assign((size_t)(M - 1), 0);
+            c->slot_flags.assign((size_t)M, FLAG_SOLID);
+            c->nbt.assign((size_t)(Q - 1) * (size_t)nf, 0);
+        } catch (...) {
+            return fail(c, LBM_ENOMEM, "host allocation failed");
+        }
+        int64_t k = 0;
+        for (int64_t id = 0; id < n; id++)
+            if (!(c->flags[id] & FLAG_SOLID)) {
+                c->slot_of[id] = (int32_t)k;
+                c->node_of[k] = (int32_t)id;
+                k++;
+            }
+        for (int64_t g = 0; g < ng; g++) {
+            c->slot_of[ghosts[g]] = (int32_t)(nf + g);
+            c->node_of[nf + g] = (int32_t)ghosts[g];
+        }
+        for (int64_t sl = 0; sl < M - 1; sl++) c->slot_flags[sl] = c->flags[c->node_of[sl]];
+        for (int64_t f = 0; f < nf; f++) {
+            const int64_t id = c->node_of[f];
+            const int64_t x = id % nx, y = (id / nx) % ny, z = id / ((int64_t)nx * ny);
+            for (int i = 1; i < Q; i++) {
+                const int64_t nb = id_of(wrapi(x + cv[i][0], nx), wrapi(y + cv[i][1], ny),
+                                         D == 3 ? wrapi(z + cv[i][2], nz) : 0);
+                c->nbt[(size_t)(i - 1) * nf + f] = (uint32_t)c->slot_of[nb];
+            }
+        }
+        c->M = M;
+        c->S = (M + 127) / 128 * 128;
+        c->sp.n = M;
+        c->sp.S = c->S;
+    }
     // Device layout (all 256-byte aligned).
     const size_t es = elem_size(c->P.precision), fs = phi_size(c->P.precision);
     const size_t plane = align256((size_t)c->S * es), tplane = align256((size_t)c->S * fs);
@@ -452,7 +507,7 @@ int lbm_set_geometry(lbm_ctx* c, const lbm_solid* solids, int32_t count) {
     off += (size_t)Q * tplane;                          // B
     off += 2 * (size_t)(D + 1) * tplane;                // G[2]
     off += 2 * align256((size_t)c->S * fs);             // phi[2]
-    off += align256((size_t)n);                         // flags
+    off += align256((size_t)(c->sparse ? c->M : n));    // flags
     off += align256((size_t)ng * 4);                    // g_node
     off += align256((size_t)ng * NC * 4);               // g_corner
     off += align256((size_t)ng * NC * fs);              // g_w
@@ -461,7 +516,9 @@ int lbm_set_geometry(lbm_ctx* c, const lbm_solid* solids, int32_t count) {
     c->fluid.reserve((size_t)(n - c->n_solid));
     for (int64_t id = 0; id < n; id++)
         if (!(c->flags[id] & FLAG_SOLID)) c->fluid.push_back((int32_t)id);
+    if (c->sparse) std::vector<int32_t>().swap(c->fluid);
     off += align256(c->fluid.size() * 4);               // fluid list
+    off += align256(c->nbt.size() * 4);                 // neighbour slots (sparse layout)
     off += 4 * align256((size_t)c->S * 8);              // aux
     off += align256((size_t)REDUCE_BLOCKS * 8 * 8);     // partial
     off += align256(8 * 8);                             // result
@@ -502,31 +559,50 @@ int lbm_bind(lbm_ctx* c, void* dev, size_t bytes, void* stream) {
     d.B = p; p += (size_t)Q * tplane;
     for (int b = 0; b < 2; b++) { d.G[b] = p; p += (size_t)(c->D + 1) * tplane; }
     for (int b = 0; b < 2; b++) { d.phi[b] = p; p += align256((size_t)c->S * fs); }
-    d.flags = (uint8_t*)p; p += align256((size_t)c->n);
+    d.flags = (uint8_t*)p; p += align256((size_t)(c->sparse ? c->M : c->n));
     d.g_node = (int32_t*)p; p += align256((size_t)ng * 4);
     d.g_corner = (int32_t*)p; p += align256((size_t)ng * NC * 4);
     d.g_w = p; p += align256((size_t)ng * NC * fs);
     d.g_mask = (uint8_t*)p; p += align256((size_t)ng);
     d.fluid = (int32_t*)p; p += align256(c->fluid.size() * 4);
+    d.nbt = (uint32_t*)p; p += align256(c->nbt.size() * 4);
     d.aux = (double*)p; p += 4 * align256((size_t)c->S * 8);
     d.partial = (double*)p; p += align256((size_t)REDUCE_BLOCKS * 8 * 8);
     d.result = (double*)p; p += align256(8 * 8);
     d.nonfinite = (int64_t*)p; p += align256((size_t)(REDUCE_BLOCKS + 1) * 8);
     d.n_ghost = (int32_t)ng;
     d.fused = (c->P.options & LBM_OPT_FUSED) ? 1 : 0;
-    d.n_fluid = (int64_t)c->fluid.size();
+    d.n_fluid = c->sparse ? c->n - c->n_solid : (int64_t)c->fluid.size();
     // Fluid-list launches (opt-in: on a 60 %-solid packing they measured
     // slower than the dense grid, whose rows keep the loads coalesced).
     d.list = (c->P.options & LBM_OPT_FLUID_LIST) ? 1 : 0;
-    // Upload the geometry.
+    d.sparse = c->sparse ? 1 : 0;
+    // Upload the geometry (slot-indexed in the sparse layout).
     hipStream_t st = c->stream;
-    HIPCHK(c, hipMemcpyAsync(d.flags, c->flags.data(), (size_t)c->n, hipMemcpyHostToDevice, st), "upload flags");
-    if (d.n_fluid > 0)
-        HIPCHK(c, hipMemcpyAsync(d.fluid, c->fluid.data(), (size_t)d.n_fluid * 4, hipMemcpyHostToDevice, st),
+    std::vector<int32_t> g_node_up, g_corner_up;
+    const int32_t* g_node_src = c->g_node.data();
+    const int32_t* g_corner_src = c->g_corner.data();
+    if (c->sparse) {
+        g_node_up.resize(c->g_node.size());
+        g_corner_up.resize(c->g_corner.size());
+        for (size_t k = 0; k < g_node_up.size(); k++) g_node_up[k] = c->slot_of[c->g_node[k]];
+        for (size_t k = 0; k < g_corner_up.size(); k++) g_corner_up[k] = c->slot_of[c->g_corner[k]];
+        g_node_src = g_node_up.data();
+        g_corner_src = g_corner_up.data();
+        HIPCHK(c, hipMemcpyAsync(d.flags, c->slot_flags.data(), (size_t)c->M, hipMemcpyHostToDevice, st),
+               "upload flags");
+        if (!c->nbt.empty())
+            HIPCHK(c, hipMemcpyAsync(d.nbt, c->nbt.data(), c->nbt.size() * 4, hipMemcpyHostToDevice, st),
+                   "upload neighbour slots");
+    } else {
+        HIPCHK(c, hipMemcpyAsync(d.flags, c->flags.data(), (size_t)c->n, hipMemcpyHostToDevice, st), "upload flags");
+    }
+    if (!c->fluid.empty())   // box layout only (the sparse layout keeps no list)
+        HIPCHK(c, hipMemcpyAsync(d.fluid, c->fluid.data(), c->fluid.size() * 4, hipMemcpyHostToDevice, st),
                "upload fluid list");
     if (ng > 0) {
-        HIPCHK(c, hipMemcpyAsync(d.g_node, c->g_node.data(), (size_t)ng * 4, hipMemcpyHostToDevice, st), "upload ghosts");
-        HIPCHK(c, hipMemcpyAsync(d.g_corner, c->g_corner.data(), (size_t)ng * NC * 4, hipMemcpyHostToDevice, st),
+        HIPCHK(c, hipMemcpyAsync(d.g_node, g_node_src, (size_t)ng * 4, hipMemcpyHostToDevice, st), "upload ghosts");
+        HIPCHK(c, hipMemcpyAsync(d.g_corner, g_corner_src, (size_t)ng * NC * 4, hipMemcpyHostToDevice, st),
                "upload corners");
         HIPCHK(c, hipMemcpyAsync(d.g_mask, c->g_mask.data(), (size_t)ng, hipMemcpyHostToDevice, st), "upload mask");
         if (c->P.precision == LBM_FP64) {
@@ -565,8 +641,35 @@ int lbm_set_wetting(lbm_ctx* c, double theta_deg) {
     return LBM_OK;
 }
 
-static int upload_aux(lbm_ctx* c, const double* src, int64_t count, int64_t plane_off) {
-    HIPCHK(c, hipMemcpyAsync(c->d.aux + plane_off, src, (size_t)count * 8, hipMemcpyHostToDevice, c->stream), "upload");
+// One FP64 plane of `count` = n box values into aux.  The sparse layout
+// gathers it into slot order first; the slot of the non-ghost solid nodes
+// takes the value of the first such node (uniform = true: all of them must
+// hold that value).
+static int upload_aux(lbm_ctx* c, const double* src, int64_t count, int64_t plane_off, bool uniform = false) {
+    if (!c->sparse) {
+        HIPCHK(c, hipMemcpyAsync(c->d.aux + plane_off, src, (size_t)count * 8, hipMemcpyHostToDevice, c->stream),
+               "upload");
+        return LBM_OK;
+    }
+    const int64_t M = c->M;
+    c->stage.resize((size_t)M);
+    for (int64_t sl = 0; sl < M - 1; sl++) c->stage[sl] = src[c->node_of[sl]];
+    bool have = false;
+    double v = 0.0;
+    for (int64_t id = 0; id < count; id++) {
+        if (c->slot_of[id] != M - 1) continue;
+        if (!have) {
+            v = src[id];
+            have = true;
+            if (!uniform) break;
+        } else if (!(src[id] == v)) {
+            return fail(c, LBM_EINVAL, "the sparse layout keeps one value for all non-ghost solid nodes");
+        }
+    }
+    c->stage[M - 1] = have ? v : 0.0;
+    HIPCHK(c, hipMemcpyAsync(c->d.aux + plane_off, c->stage.data(), (size_t)M * 8, hipMemcpyHostToDevice, c->stream),
+           "upload");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "sync");   // the staging buffer is reused
     return LBM_OK;
 }
 
@@ -624,7 +727,7 @@ int lbm_set_field(lbm_ctx* c, int field, const double* src, size_t count) {
     case LBM_FIELD_SOLID_PHI:
         if (!c->started) return fail(c, LBM_ESTATE, "set PHI first");
         if (count != (size_t)n) return fail(c, LBM_EINVAL, "SOLID_PHI needs n values");
-        if ((rc = upload_aux(c, src, n, 0)) != LBM_OK) return rc;
+        if ((rc = upload_aux(c, src, n, 0, true)) != LBM_OK) return rc;
         HIPCHK(c, launch_plane_in(lat, prec, c->d, c->sp, 2, 0, c->cur, c->stream), "plane in");
         HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
         return LBM_OK;
@@ -753,9 +856,18 @@ int lbm_observe(lbm_ctx* c, lbm_obs* out) {
     return LBM_OK;
 }
 
+// One FP64 plane of aux to `count` = n box values (scattered from slot
+// order in the sparse layout).
 static int download(lbm_ctx* c, double* dst, const double* src, int64_t count) {
-    HIPCHK(c, hipMemcpyAsync(dst, src, (size_t)count * 8, hipMemcpyDeviceToHost, c->stream), "download");
+    if (!c->sparse) {
+        HIPCHK(c, hipMemcpyAsync(dst, src, (size_t)count * 8, hipMemcpyDeviceToHost, c->stream), "download");
+        HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
+        return LBM_OK;
+    }
+    c->stage.resize((size_t)c->M);
+    HIPCHK(c, hipMemcpyAsync(c->stage.data(), src, (size_t)c->M * 8, hipMemcpyDeviceToHost, c->stream), "download");
     HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
+    for (int64_t id = 0; id < count; id++) dst[id] = c->stage[c->slot_of[id]];
     return LBM_OK;
 }
 
@@ -854,6 +966,7 @@ int lbm_batch_step(lbm_batch* b, lbm_ctx* const* ctxs, const int64_t* steps, int
     for (int32_t j = 0; j < count; j++) {
         if (!ctxs[j]) return bfail(b, LBM_EINVAL, "null context");
         if (!ctxs[j]->started) return bfail(b, LBM_ESTATE, "every context must be started (PHI set)");
+        if (ctxs[j]->sparse) return bfail(b, LBM_EINVAL, "contexts with LBM_OPT_SPARSE step alone (lbm_step)");
         if (steps[j] < 0) return bfail(b, LBM_EINVAL, "steps must be >= 0");
         for (int32_t k = 0; k < j; k++)
             if (ctxs[k] == ctxs[j]) return bfail(b, LBM_EINVAL, "a context appears twice");

@@ -501,8 +501,23 @@ __global__ __launch_bounds__(256) void k_colour_planes(const T* __restrict__ B, 
     colour_planes_node<L, T>(B, phi, flags, x, S);
 }
 
-// phi = sum_i B_i (i ascending) with B_i formed from the compact record,
-// one node.
+// phi = sum_i B_i (i ascending) with B_i formed from the compact record, one
+// fluid node x with flags f and neighbour indices nb.
+template <class L, class T, class SN>
+__device__ __forceinline__ void colour_compact_core(const SN* __restrict__ N, const T* __restrict__ phi_prev,
+                                                    const T* __restrict__ G, const uint8_t* __restrict__ flags,
+                                                    T* __restrict__ phi, const KParams<T, L::Q>& P, uint32_t x,
+                                                    uint8_t f, const uint32_t (&nb)[L::Q]) {
+    const bool near = (f & FLAG_NEAR_SOLID) != 0;
+    T acc = 0;
+    static_for<0, L::Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        acc += compact_B<L, T, SN, i>(N, phi_prev, G, flags, P, x, nb, near);
+    });
+    st(phi, x, acc);
+}
+
+// The same for the node at (ix, iy, iz) of the box layout.
 template <class L, class T, class SN>
 __device__ __forceinline__ void colour_compact_node(const SN* __restrict__ N, const T* __restrict__ phi_prev,
                                                     const T* __restrict__ G, const uint8_t* __restrict__ flags,
@@ -513,13 +528,7 @@ __device__ __forceinline__ void colour_compact_node(const SN* __restrict__ N, co
     if (f & FLAG_SOLID) return;
     uint32_t nb[L::Q];
     neighbours<L>(ix, iy, iz, P.nx, P.ny, P.nz, nb);
-    const bool near = (f & FLAG_NEAR_SOLID) != 0;
-    T acc = 0;
-    static_for<0, L::Q>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        acc += compact_B<L, T, SN, i>(N, phi_prev, G, flags, P, x, nb, near);
-    });
-    st(phi, x, acc);
+    colour_compact_core<L, T, SN>(N, phi_prev, G, flags, phi, P, x, f, nb);
 }
 
 template <class L, class T, class SN>
@@ -976,16 +985,11 @@ __global__ __launch_bounds__(256) void k_ghost(const int32_t* __restrict__ g_nod
 // halfway bounce-back, one node.  Writes the streamed N* and the node's
 // compact liquid record (G, p).
 template <class L, class T, class SN, bool WG = true>
-__device__ __forceinline__ void collide_node(const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
+__device__ __forceinline__ void collide_core(const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
                                              T* __restrict__ Gdst, const T* __restrict__ phi,
-                                             const uint8_t* __restrict__ flags, const KParams<T, L::Q>& P, int ix,
-                                             int iy, int iz) {
+                                             const uint8_t* __restrict__ flags, const KParams<T, L::Q>& P,
+                                             uint32_t x, uint8_t f, const uint32_t (&nb)[L::Q]) {
     constexpr int Q = L::Q;
-    const uint32_t x = (uint32_t)ix + (uint32_t)P.nx * ((uint32_t)iy + (uint32_t)P.ny * (uint32_t)iz);
-    const uint8_t f = ld(flags, x);
-    if (f & FLAG_SOLID) return;
-    uint32_t nb[Q];
-    neighbours<L>(ix, iy, iz, P.nx, P.ny, P.nz, nb);
     using NS = NStore<T, SN>;
     const int64_t S = P.S;
     T N[Q], ph[Q];
@@ -1022,6 +1026,20 @@ __device__ __forceinline__ void collide_node(const SN* __restrict__ Nsrc, SN* __
         for (int a = 0; a < L::D; a++) st(Gdst + (int64_t)a * S, x, G[a]);
     }
     st(Gdst + (int64_t)GRec<L>::P * S, x, m.p);
+}
+
+// The same for the node at (ix, iy, iz) of the box layout.
+template <class L, class T, class SN, bool WG = true>
+__device__ __forceinline__ void collide_node(const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
+                                             T* __restrict__ Gdst, const T* __restrict__ phi,
+                                             const uint8_t* __restrict__ flags, const KParams<T, L::Q>& P, int ix,
+                                             int iy, int iz) {
+    const uint32_t x = (uint32_t)ix + (uint32_t)P.nx * ((uint32_t)iy + (uint32_t)P.ny * (uint32_t)iz);
+    const uint8_t f = ld(flags, x);
+    if (f & FLAG_SOLID) return;
+    uint32_t nb[L::Q];
+    neighbours<L>(ix, iy, iz, P.nx, P.ny, P.nz, nb);
+    collide_core<L, T, SN, WG>(Nsrc, Ndst, Gdst, phi, flags, P, x, f, nb);
 }
 
 // One thread per node of an x-row.  WG = false leaves the G planes of the
@@ -1068,6 +1086,120 @@ __global__ __launch_bounds__(256) void k_collide_list(const int32_t* __restrict_
     int ix, iy, iz;
     list_coords(list[k], P.nx, P.ny, ix, iy, iz);
     collide_node<L, T, SN>(Nsrc, Ndst, Gdst, phi, flags, P, ix, iy, iz);
+}
+
+// Fluid-only ("sparse") layout for packings: node slots are the fluid nodes
+// (ascending box index), then the ghost nodes, then one slot that stands
+// for every other solid node; every plane has one entry per slot.
+// nbt[(i - 1) n_fluid + k] is the slot of fluid node k + c_i (a ghost slot
+// where the neighbour is solid).  The per-node functions are the box
+// layout's, so a step computes the same values bit for bit; only the
+// launches cover the fluid slots instead of the box.
+// Block order of the sparse launches.  The hardware deals consecutive
+// blocks round-robin to the eight XCDs; with LBM_SPARSE_XCD the blocks are
+// renumbered so that each XCD walks one contiguous eighth of the slots (its
+// L2 then still holds the neighbour planes a gather needs).
+#ifndef LBM_SPARSE_XCD
+#define LBM_SPARSE_XCD 0
+#endif
+__device__ __forceinline__ int64_t sparse_block() {
+#if LBM_SPARSE_XCD
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    const uint32_t q = nb / 8, r = nb % 8, x = b % 8;
+    return (int64_t)(x * q + (x < r ? x : r) + b / 8);
+#else
+    return blockIdx.x;
+#endif
+}
+
+template <class L>
+__device__ __forceinline__ void sparse_neighbours(const uint32_t* __restrict__ nbt, int64_t nf, uint32_t k,
+                                                  uint32_t (&nb)[L::Q]) {
+    nb[0] = k;
+#pragma unroll
+    for (int i = 1; i < L::Q; i++) nb[i] = nbt[(int64_t)(i - 1) * nf + k];
+}
+
+template <class L, class T, class SN>
+__global__ __launch_bounds__(256) void k_colour_sparse(const uint32_t* __restrict__ nbt, int64_t nf,
+                                                       const SN* __restrict__ N, const T* __restrict__ phi_prev,
+                                                       const T* __restrict__ G, const uint8_t* __restrict__ flags,
+                                                       T* __restrict__ phi, KParams<T, L::Q> P) {
+    const int64_t k = sparse_block() * blockDim.x + threadIdx.x;
+    if (k >= nf) return;
+    uint32_t nb[L::Q];
+    sparse_neighbours<L>(nbt, nf, (uint32_t)k, nb);
+    colour_compact_core<L, T, SN>(N, phi_prev, G, flags, phi, P, (uint32_t)k, ld(flags, (uint32_t)k), nb);
+}
+
+template <class L, class T, class SN>
+__global__ __launch_bounds__(256) void k_collide_sparse(const uint32_t* __restrict__ nbt, int64_t nf,
+                                                        const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
+                                                        T* __restrict__ Gdst, const T* __restrict__ phi,
+                                                        const uint8_t* __restrict__ flags, KParams<T, L::Q> P) {
+    const int64_t k = sparse_block() * blockDim.x + threadIdx.x;
+    if (k >= nf) return;
+    uint32_t nb[L::Q];
+    sparse_neighbours<L>(nbt, nf, (uint32_t)k, nb);
+    collide_core<L, T, SN, true>(Nsrc, Ndst, Gdst, phi, flags, P, (uint32_t)k, ld(flags, (uint32_t)k), nb);
+}
+
+// u and p of every slot (solid slots get 0), sparse layout.
+template <class L, class T, class SN>
+__global__ __launch_bounds__(256) void k_macro_sparse(const uint32_t* __restrict__ nbt, int64_t nf,
+                                                      const SN* __restrict__ Nsrc, const T* __restrict__ phi,
+                                                      const uint8_t* __restrict__ flags, KParams<T, L::Q> P,
+                                                      int64_t n, double* __restrict__ aux) {
+    constexpr int Q = L::Q;
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const int64_t S = P.S;
+    if ((flags[x] & FLAG_SOLID) || x >= nf) {
+        aux[x] = 0.0;
+        aux[S + x] = 0.0;
+        aux[2 * S + x] = 0.0;
+        aux[3 * S + x] = 0.0;
+        return;
+    }
+    uint32_t nb[Q];
+    sparse_neighbours<L>(nbt, nf, (uint32_t)x, nb);
+    T N[Q], ph[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) N[i] = NStore<T, SN>::dec(Nsrc[(int64_t)i * S + x], P.n_s);
+#pragma unroll
+    for (int i = 0; i < Q; i++) ph[i] = phi[nb[i]];
+    Macro<T> m;
+    T Pi[6];
+    macro_stage<L, T>(N, ph, P, m, Pi);
+    aux[x] = (double)m.u[0];
+    aux[S + x] = (double)m.u[1];
+    aux[2 * S + x] = (double)m.u[2];
+    aux[3 * S + x] = (double)m.p;
+}
+
+// One direction plane of B from the compact record into FP64, sparse layout.
+template <class L, class T, class SN>
+__global__ __launch_bounds__(256) void k_compact_B_sparse(const uint32_t* __restrict__ nbt, int64_t nf,
+                                                          const SN* __restrict__ N, const T* __restrict__ phi_prev,
+                                                          const T* __restrict__ G, const uint8_t* __restrict__ flags,
+                                                          KParams<T, L::Q> P, int dir, int64_t n,
+                                                          double* __restrict__ out) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    const uint8_t f = flags[x];
+    if ((f & FLAG_SOLID) || x >= nf) {
+        out[x] = 0.0;
+        return;
+    }
+    uint32_t nb[L::Q];
+    sparse_neighbours<L>(nbt, nf, (uint32_t)x, nb);
+    const bool near = (f & FLAG_NEAR_SOLID) != 0;
+    T v = 0;
+    static_for<0, L::Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        if (i == dir) v = compact_B<L, T, SN, i>(N, phi_prev, G, flags, P, (uint32_t)x, nb, near);
+    });
+    out[x] = (double)v;
 }
 
 // Macroscopic fields (u, p) of every node into FP64 planes; solids get 0.
@@ -1713,7 +1845,7 @@ static hipError_t fused_phase_t(int phase, const DevState& d, const StepParams& 
 // dense-grid, two-launch path).
 template <class L>
 static inline bool g_mode(const DevState& d, const StepParams& p) {
-    return LBM_G_RECOMPUTE && L::D == 3 && !d.list && !d.fused && colour_tile_ok(p);
+    return LBM_G_RECOMPUTE && L::D == 3 && !d.list && !d.sparse && !d.fused && colour_tile_ok(p);
 }
 
 template <class L, class T, class SN>
@@ -1729,6 +1861,13 @@ static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int
                                (const T*)d.B, work, d.flags, p.n, p.S);
         } else {
             const KParams<T, L::Q> kp = make_kparams<T, L, SN>(p);
+            if (d.sparse) {
+                if (d.n_fluid > 0)
+                    hipLaunchKernelGGL((k_colour_sparse<L, T, SN>), dim3(blocks_for(d.n_fluid, 256)), dim3(256), 0,
+                                       st, d.nbt, d.n_fluid, (const SN*)d.N[cur], (const T*)d.phi[ps],
+                                       (const T*)d.G[cur], d.flags, work, kp);
+                return hipGetLastError();
+            }
             if (d.list) {
                 if (d.n_fluid > 0)
                     hipLaunchKernelGGL((k_colour_list<L, T, SN>), dim3(blocks_for(d.n_fluid, 256)), dim3(256), 0, st,
@@ -1765,6 +1904,13 @@ static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int
         }
     } else {
         const KParams<T, L::Q> kp = make_kparams<T, L, SN>(p);
+        if (d.sparse) {
+            if (d.n_fluid > 0)
+                hipLaunchKernelGGL((k_collide_sparse<L, T, SN>), dim3(blocks_for(d.n_fluid, 256)), dim3(256), 0, st,
+                                   d.nbt, d.n_fluid, (const SN*)d.N[cur], (SN*)d.N[1 - cur], (T*)d.G[1 - cur],
+                                   (const T*)work, d.flags, kp);
+            return hipGetLastError();
+        }
         if (d.list) {
             if (d.n_fluid > 0)
                 hipLaunchKernelGGL((k_collide_list<L, T, SN>), dim3(blocks_for(d.n_fluid, 256)), dim3(256), 0, st,
@@ -1806,6 +1952,11 @@ static hipError_t step_t(const DevState& d, const StepParams& p, int cur, int ps
 template <class L, class T, class SN>
 static hipError_t macro_t(const DevState& d, const StepParams& p, int cur, int ps, hipStream_t st) {
     const KParams<T, L::Q> kp = make_kparams<T, L, SN>(p);
+    if (d.sparse) {
+        hipLaunchKernelGGL((k_macro_sparse<L, T, SN>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st, d.nbt,
+                           d.n_fluid, (const SN*)d.N[cur], (const T*)d.phi[1 - ps], d.flags, kp, p.n, d.aux);
+        return hipGetLastError();
+    }
     const int bx = row_block(p.nx);
     hipLaunchKernelGGL((k_macro<L, T, SN>), row_grid(p, bx), dim3(bx), 0, st, (const SN*)d.N[cur],
                        (const T*)d.phi[1 - ps], d.flags, kp, d.aux);
@@ -1842,6 +1993,12 @@ static hipError_t plane_out_t(const DevState& d, const StepParams& p, int which,
                               int from_planes, hipStream_t st) {
     if (which == 1 && !from_planes) {
         const KParams<T, L::Q> kp = make_kparams<T, L, SN>(p);
+        if (d.sparse) {
+            hipLaunchKernelGGL((k_compact_B_sparse<L, T, SN>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st, d.nbt,
+                               d.n_fluid, (const SN*)d.N[cur], (const T*)d.phi[ps], (const T*)d.G[cur], d.flags, kp,
+                               dir, p.n, d.aux);
+            return hipGetLastError();
+        }
         const int bx = row_block(p.nx);
         hipLaunchKernelGGL((k_compact_B_plane<L, T, SN>), row_grid(p, bx), dim3(bx), 0, st, (const SN*)d.N[cur],
                            (const T*)d.phi[ps], (const T*)d.G[cur], d.flags, kp, dir, d.aux);

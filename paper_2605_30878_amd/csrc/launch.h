@@ -48,6 +48,9 @@ struct DevState {
     int32_t* fluid;     // [n_fluid] fluid node ids, ascending
     int64_t n_fluid;
     int32_t list;       // 1: colour and collide launch one thread per listed fluid node
+    int32_t sparse;     // 1: fluid-only layout: planes hold one entry per slot (fluid nodes,
+                        //    then ghost nodes, then one slot for every other solid node)
+    uint32_t* nbt;      // [Q-1][n_fluid] sparse layout: slot of fluid node k + c_i
 };
 
 constexpr int REDUCE_BLOCKS = 1024;

@@ -24,6 +24,7 @@ OPT_FLUID_PROBE = 2
 OPT_FLUID_LIST = 4
 OPT_GRAPH = 8
 OPT_FILL_DEAD_ENDS = 16
+OPT_SPARSE = 32
 FIELD_PHI, FIELD_N, FIELD_B, FIELD_U, FIELD_P, FIELD_SOLID_PHI, FIELD_FLAGS, FIELD_N_OFFSET = range(8)
 FLAG_SOLID, FLAG_NEAR_SOLID, FLAG_GHOST = 1, 2, 4
 

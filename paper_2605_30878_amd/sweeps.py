@@ -108,14 +108,15 @@ def sphere_sweep(thetas=(30.0, 60.0, 90.0, 120.0, 150.0), n: int = 256, steps: i
 
 
 def porous_run(n: int = 384, steps: int = 50000, every: int = 2500, precision: int = W.FP32,
-               theta: float = 45.0) -> List[Dict[str, float]]:
+               theta: float = 45.0, sparse: bool = True) -> List[Dict[str, float]]:
     """The dynamic contact line in the sphere packing (fluid-only probe):
     liquid saturation, liquid centroid along the flow (circular mean, the box
-    is periodic), max|u| and x-momentum every `every` steps."""
+    is periodic), max|u| and x-momentum every `every` steps, in the
+    fluid-only storage layout unless `sparse` is False."""
     import sys
     import time
     wl = W.porous_d3q19(n=n, precision=precision).with_(theta=theta)
-    sim = lbm.Simulation(wl, W.initial_phi(wl))
+    sim = lbm.Simulation(wl, W.initial_phi(wl), options=lbm.OPT_SPARSE if sparse else 0)
     flags = sim.read(lbm.FIELD_FLAGS)
     fluid = (flags.astype(np.int64) & lbm.FLAG_SOLID) == 0
     ang = np.exp(2j * math.pi * (np.arange(wl.nodes) % n) / n)[fluid]

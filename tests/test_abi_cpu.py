@@ -116,7 +116,9 @@ def test_device_bytes_cover_the_state():
                        W.Solid(1, (0.0, 24.5, 0.0), normal=(0.3, -1.0, 0.0))]),
     W.Workload(name="wrap3", lattice=W.D3Q19, shape=(21, 18, 17), theta=45.0,
                solids=[W.Solid(0, (0.0, 17.0, 8.0), 5.5), W.Solid(0, (10.0, 9.0, 8.0), 4.0)]),
-], ids=["cyl128", "sphere64", "plate", "wrap2d", "wrap3d"])
+    # a packing with its dead-end nodes filled (LBM_OPT_FILL_DEAD_ENDS)
+    W.porous_d3q19(n=40, sphere_radius=5.0, porosity=0.40, seed=1, precision=W.FP64, front=10.0),
+], ids=["cyl128", "sphere64", "plate", "wrap2d", "wrap3d", "porous40_fill"])
 def test_node_classes_match_oracle(wl):
     lib = lbm.load_library()
     rc, h = _create(wl)
@@ -142,3 +144,34 @@ def test_lattice_tables():
         assert len({tuple(v) for v in c}) == len(c)
         assert (c.sum(axis=0) == 0).all()
     assert np.array_equal(c3[:9], c2)
+
+
+def test_sparse_option_combinations_and_bytes():
+    """LBM_OPT_SPARSE excludes the fused and fluid-list forms; on a packing
+    its device buffer holds one entry per slot (fluid nodes, ghosts and one
+    solid slot) plus Q - 1 neighbour slots per fluid node, less than the
+    box layout needs."""
+    lib = lbm.load_library()
+    wl = W.porous_d3q19(n=40, sphere_radius=5.0, porosity=0.40, seed=0, precision=W.FP32, front=10.0)
+    for bad in (lbm.OPT_SPARSE | lbm.OPT_FUSED, lbm.OPT_SPARSE | lbm.OPT_FLUID_LIST):
+        p = lbm.make_params(wl, bad)
+        h = C.c_void_p()
+        assert lib.lbm_create(C.byref(p), C.byref(h)) == lbm.EINVAL
+    sizes = {}
+    for opt in (0, lbm.OPT_SPARSE):
+        p = lbm.make_params(wl, opt)
+        h = C.c_void_p()
+        assert lib.lbm_create(C.byref(p), C.byref(h)) == lbm.OK
+        assert lib.lbm_set_geometry(h, lbm.make_solids(wl.solids), len(wl.solids)) == lbm.OK
+        nbytes = C.c_size_t()
+        assert lib.lbm_device_bytes(h, C.byref(nbytes)) == lbm.OK
+        sizes[opt] = nbytes.value
+        f = np.zeros(wl.nodes)
+        assert lib.lbm_read_field(h, lbm.FIELD_FLAGS, f.ctypes.data_as(C.POINTER(C.c_double)), wl.nodes) == lbm.OK
+        lib.lbm_destroy(h)
+    flags = f.astype(np.int64)
+    nf = int(((flags & lbm.FLAG_SOLID) == 0).sum())
+    ng = int(((flags & lbm.FLAG_GHOST) > 0).sum())
+    slots = nf + ng + 1
+    assert sizes[lbm.OPT_SPARSE] >= (3 * 19 + 2 * 4) * slots * 4 + 18 * nf * 4
+    assert sizes[lbm.OPT_SPARSE] < sizes[0]

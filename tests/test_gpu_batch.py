@@ -140,3 +140,18 @@ def test_batch_after_tiled_single_steps(prec):
     batch.close()
     for s in (a, b, other):
         s.close()
+
+
+def test_batch_rejects_sparse_layout():
+    """Contexts in the fluid-only layout step alone: lbm_batch_step refuses them."""
+    lbm = _lbm()
+    wl = W.cylinder_d2q9_128()
+    a = lbm.Simulation(wl, W.initial_phi(wl))
+    b = lbm.Simulation(wl, W.initial_phi(wl), options=lbm.OPT_SPARSE)
+    batch = lbm.Batch(max_jobs=2)
+    with pytest.raises(lbm.LbmError):
+        batch.step([a, b], [1, 1])
+    batch.step([a], [1])
+    batch.close()
+    a.close()
+    b.close()

@@ -361,3 +361,67 @@ def test_step_graph_replays_equal_direct_launches(wl):
             assert np.array_equal(a.read(f), b.read(f)), (k, f)
     a.close()
     b.close()
+
+
+def _packing40(prec, probe=1, fill=1, seed=0):
+    wl = W.porous_d3q19(n=40, sphere_radius=5.0, porosity=0.40, seed=seed, precision=prec, front=10.0,
+                        probe=probe, fill=fill)
+    return wl.with_(g=(1e-5, 0.0, 0.0))
+
+
+@pytest.mark.parametrize("case", ["porous40", "porous40_all_corners", "cyl128"])
+def test_sparse_layout_fp64_parity(case):
+    """The fluid-only layout (LBM_OPT_SPARSE: planes over fluid and ghost
+    slots, neighbours from a slot table) against the oracle: the packing in
+    the porous workload's setting, the packing with all probe corners (probes
+    then read the shared slot of the non-ghost solid nodes), and the D2Q9
+    cylinder."""
+    if case == "porous40":
+        _run_pair(_packing40(W.FP64), [1, 30, 300], TOL64, options=32)   # LBM_OPT_SPARSE
+    elif case == "porous40_all_corners":
+        _run_pair(_packing40(W.FP64, probe=0, fill=0), [1, 30], TOL64, options=32)
+    else:
+        _run_pair(W.cylinder_d2q9_128(theta=30.0), [1, 50, 500], TOL64, options=32)
+
+
+@pytest.mark.parametrize("prec", [W.FP32, W.FP16_OFS], ids=["f32", "fp16ofs"])
+def test_sparse_layout_equals_box_layout(prec):
+    """Both layouts call the same per-node functions: N (stored offsets), B,
+    phi, solid phi, u and p are identical bit for bit after 1 and 60 steps
+    (the diagnostics, summed in another order, agree to rounding).  A state
+    read from the sparse run restores into a fresh sparse run that continues
+    bit-identically."""
+    lbm = _lbm()
+    wl = _packing40(prec)
+    phi0 = W.initial_phi(wl)
+    a = lbm.Simulation(wl, phi0)
+    b = lbm.Simulation(wl, phi0, options=lbm.OPT_SPARSE)
+    assert b.device_bytes < a.device_bytes
+    fields = [lbm.FIELD_N_OFFSET, lbm.FIELD_B, lbm.FIELD_PHI, lbm.FIELD_SOLID_PHI, lbm.FIELD_U, lbm.FIELD_P]
+    for n in (1, 59):
+        a.step(n)
+        b.step(n)
+        for f in fields:
+            assert np.array_equal(a.read(f), b.read(f)), (n, f)
+        oa, ob = a.observe(), b.observe()
+        assert oa["n_fluid"] == ob["n_fluid"] and oa["n_ghost"] == ob["n_ghost"]
+        for k in ("mass_blue", "mass_red", "kinetic_energy", "max_speed"):
+            assert abs(oa[k] - ob[k]) <= 1e-12 * max(abs(oa[k]), 1e-30), (k, oa[k], ob[k])
+    N, B, S = b.read(lbm.FIELD_N_OFFSET), b.read(lbm.FIELD_B), b.read(lbm.FIELD_SOLID_PHI)
+    c = lbm.Simulation(wl, phi0, options=lbm.OPT_SPARSE)
+    c.set_field(lbm.FIELD_N_OFFSET, N)
+    c.set_field(lbm.FIELD_B, B)
+    c.set_field(lbm.FIELD_SOLID_PHI, S)
+    b.step(10)
+    c.step(10)
+    for f in fields:
+        assert np.array_equal(b.read(f), c.read(f)), f
+    # one value for every non-ghost solid node is all the layout keeps
+    flags = b.read(lbm.FIELD_FLAGS).astype(np.int64)
+    inner = np.flatnonzero(((flags & lbm.FLAG_SOLID) > 0) & ((flags & lbm.FLAG_GHOST) == 0))
+    S2 = S.copy()
+    S2[inner[0]] += 0.25
+    with pytest.raises(lbm.LbmError):
+        c.set_field(lbm.FIELD_SOLID_PHI, S2)
+    for s in (a, b, c):
+        s.close()
