@@ -53,6 +53,11 @@ struct lbm_ctx {
     std::string err;
 };
 
+// Fluid slot order of the sparse layout: 0 = box order, b > 0 = b^3 bricks.
+#ifndef LBM_SPARSE_BRICK
+#define LBM_SPARSE_BRICK 0
+#endif
+
 static thread_local std::string g_create_error;
 
 static int fail(lbm_ctx* c, int code, const std::string& msg) {
@@ -457,8 +462,8 @@ int lbm_set_geometry(lbm_ctx* c, const lbm_solid* solids, int32_t count) {
         c->g_mask[g] = mask;
     }
     if (c->sparse) {
-        // Slots: fluid nodes in box order, ghost nodes in list order, then
-        // the slot of every other solid node.
+        // Slots: fluid nodes, ghost nodes in list order, then the slot of
+        // every other solid node.
         const int64_t nf = n - nsolid;
         const int64_t M = nf + ng + 1;
         if ((uint64_t)((M + 127) / 128 * 128) * std::max(elem_size(c->P.precision), phi_size(c->P.precision)) >
@@ -474,12 +479,25 @@ int lbm_set_geometry(lbm_ctx* c, const lbm_solid* solids, int32_t count) {
             return fail(c, LBM_ENOMEM, "host allocation failed");
         }
         int64_t k = 0;
-        for (int64_t id = 0; id < n; id++)
-            if (!(c->flags[id] & FLAG_SOLID)) {
-                c->slot_of[id] = (int32_t)k;
-                c->node_of[k] = (int32_t)id;
-                k++;
-            }
+        auto take = [&](int64_t id) {
+            if (c->flags[id] & FLAG_SOLID) return;
+            c->slot_of[id] = (int32_t)k;
+            c->node_of[k] = (int32_t)id;
+            k++;
+        };
+        if (LBM_SPARSE_BRICK > 0) {
+            // fluid slots brick by brick (bricks and the nodes in a brick
+            // in box order), so that most neighbours share a brick
+            const int64_t b = LBM_SPARSE_BRICK, bzs = D == 3 ? b : 1;
+            for (int64_t z0 = 0; z0 < nz; z0 += bzs)
+                for (int64_t y0 = 0; y0 < ny; y0 += b)
+                    for (int64_t x0 = 0; x0 < nx; x0 += b)
+                        for (int64_t z = z0; z < std::min<int64_t>(z0 + bzs, nz); z++)
+                            for (int64_t y = y0; y < std::min<int64_t>(y0 + b, ny); y++)
+                                for (int64_t x = x0; x < std::min<int64_t>(x0 + b, nx); x++) take(id_of(x, y, z));
+        } else {
+            for (int64_t id = 0; id < n; id++) take(id);
+        }
         for (int64_t g = 0; g < ng; g++) {
             c->slot_of[ghosts[g]] = (int32_t)(nf + g);
             c->node_of[nf + g] = (int32_t)ghosts[g];
