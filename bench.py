@@ -66,8 +66,48 @@ def cpu_baseline(wl, steps: int):
     dt = time.perf_counter() - t0
     del sim
     return {"value": wl.nodes * steps / (dt * 1e6), "unit": "MLUPS", "cores": threads, "kind": "oracle",
-            "sample": f"{steps} steps of the full {wl.shape[0]}x{wl.shape[1]}x{wl.shape[2]} D3Q19 box "
+            "sample": f"{steps} steps of the full {wl.shape[0]}x{wl.shape[1]}x{wl.shape[2]} "
+                      f"{W.lattice_name(wl.lattice)} box "
                       f"(FP64 oracle, OpenMP over nodes), after 1 untimed step"}
+
+
+CPU_WINDOWS = {
+    # name: (workload factory, steps); the oracle in FP64, as in cpu_baseline.
+    # The 384^3 packing is left out: the oracle tests every node against
+    # every one of its 4,694 spheres when it builds the geometry.
+    "d2q9_cylinder_128": (lambda W: W.cylinder_d2q9_128(), 2000),
+    "d3q19_sphere_64": (lambda W: W.sphere_d3q19(64, precision=W.FP64), 200),
+    "d3q19_sphere_256": (lambda W: W.sphere_d3q19(256, precision=W.FP64), 3),
+}
+
+
+def cpu_window(name: str) -> dict:
+    """One oracle timing window (this process's OpenMP threads)."""
+    from paper_2605_30878_amd import workloads as W
+
+    make, steps = CPU_WINDOWS[name]
+    wl = make(W)
+    r = cpu_baseline(wl, steps)
+    r.update({"window": name, "steps": steps, "nodes": wl.nodes})
+    return r
+
+
+def cpu_windows(threads) -> list:
+    """Every window at each thread count, each in a child process started
+    with OMP_NUM_THREADS set (the OpenMP pool is sized at start-up).  No GPU
+    is used."""
+    import subprocess
+
+    out = []
+    for name in CPU_WINDOWS:
+        for t in threads:
+            env = dict(os.environ, OMP_NUM_THREADS=str(t))
+            res = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-window", name],
+                                 env=env, capture_output=True, text=True, check=True)
+            rec = json.loads(res.stdout.strip().splitlines()[-1])
+            print(f"[cpu] {rec}", file=sys.stderr, flush=True)
+            out.append(rec)
+    return out
 
 
 def main() -> int:
@@ -92,7 +132,20 @@ def main() -> int:
                     help="served mix at full size: 256 requests, 2000-20000 steps each")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (for HBM counter calibration)")
+    ap.add_argument("--cpu-windows", action="store_true",
+                    help="only time the FP64 oracle on the host over fixed windows of several workloads, "
+                         "with all cores and with one thread (no GPU use)")
+    ap.add_argument("--cpu-window", default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+
+    if args.cpu_window:
+        print(json.dumps(cpu_window(args.cpu_window)), flush=True)
+        return 0
+    if args.cpu_windows:
+        cores = os.cpu_count() or 1
+        print(json.dumps({"cpu_windows": cpu_windows([int(os.environ.get("OMP_NUM_THREADS", "0")) or cores, 1])}),
+              flush=True)
+        return 0
 
     if args.gpus != 1:
         print(json.dumps({"error": "the library runs one lattice on one GPU; --gpus must be 1 (multi-GPU sharding is not built)",
