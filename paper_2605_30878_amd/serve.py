@@ -5,10 +5,11 @@ a slot is free and their device footprint fits the HBM budget.  Every tick
 advances all resident runs by up to `tick_steps` steps with one
 `lbm_batch_step` call (shared launches for runs of the same lattice and
 precision); runs that arrive during a tick join at the next one, runs that
-finish leave and free their memory.  A newly admitted run is prepared on the
-host (geometry, initial field) and initialised on its own stream while the
-resident batch computes.  Latency is completion time minus arrival time on
-the host's monotonic clock.
+finish leave and free their memory.  An admitted run is prepared (initial
+field, geometry, device state on its own stream) by worker threads while the
+resident batch computes, and joins the batch at the first tick after it is
+ready.  Latency is completion time minus arrival time on the host's
+monotonic clock.
 """
 from __future__ import annotations
 
@@ -16,6 +17,7 @@ import dataclasses
 import math
 import sys
 import time
+from concurrent.futures import FIRST_COMPLETED, ThreadPoolExecutor, wait
 from typing import Dict, List, Optional, Sequence
 
 import numpy as np
@@ -100,7 +102,8 @@ def poisson_arrivals(reqs: Sequence[Request], rate: float, seed: int = 1) -> Lis
 
 class Server:
     def __init__(self, hbm_budget: float = 64e9, max_slots: int = 256, tick_steps: int = 200,
-                 device: str = "cuda:0", keep_state: bool = False, progress_s: float = 0.0):
+                 device: str = "cuda:0", keep_state: bool = False, progress_s: float = 0.0,
+                 prep_workers: int = 2):
         import torch
 
         self.torch = torch
@@ -110,14 +113,23 @@ class Server:
         self.tick = int(tick_steps)
         self.keep_state = keep_state
         self.progress_s = float(progress_s)   # > 0: a progress line on stderr this often
+        self.prep_workers = max(1, int(prep_workers))
         self.stream = torch.cuda.current_stream(self.device)
         self.init_stream = torch.cuda.Stream(device=self.device)
         self.batch = lbm.Batch(max_jobs=max_slots, device=device, stream=self.stream)
+
+    def _prepare(self, r: Request):
+        # worker thread: host set-up and the run's initial state on the init stream
+        torch = self.torch
+        with torch.cuda.stream(self.init_stream):
+            return lbm.Simulation(r.workload, W.initial_phi(r.workload), device=str(self.device),
+                                  stream=self.init_stream)
 
     def run(self, requests: Sequence[Request]) -> List[Result]:
         torch = self.torch
         pending = sorted(requests, key=lambda r: r.arrival)
         waiting: List[Request] = []
+        preparing = []  # [req, future, reserved bytes, admitted]
         resident = []   # [req, sim, remaining, admitted, bytes]
         used = 0.0
         results: List[Result] = []
@@ -125,58 +137,72 @@ class Server:
         i = 0
         busy = False
         last_report = 0.0
-        while i < len(pending) or waiting or resident:
-            now = time.monotonic() - t0
-            if self.progress_s > 0 and now - last_report >= self.progress_s:
-                last_report = now
-                print(f"[serve] t={now:.0f}s done={len(results)} resident={len(resident)} "
-                      f"waiting={len(waiting)} pending={len(pending) - i}", file=sys.stderr, flush=True)
-            while i < len(pending) and pending[i].arrival <= now:
-                waiting.append(pending[i])
-                i += 1
-            # admission by slot and HBM footprint, prepared while the GPU runs
-            while waiting and len(resident) < self.max_slots:
-                r = waiting[0]
-                need = self._footprint(r.workload)
-                if used + need > self.budget and resident:
-                    break
-                waiting.pop(0)
-                with torch.cuda.stream(self.init_stream):
-                    sim = lbm.Simulation(r.workload, W.initial_phi(r.workload), device=str(self.device),
-                                         stream=self.init_stream)
-                used += sim.device_bytes
-                resident.append([r, sim, r.steps, time.monotonic() - t0, sim.device_bytes])
-            if busy:
-                self.stream.synchronize()
-                busy = False
+        pool = ThreadPoolExecutor(max_workers=self.prep_workers)
+        try:
+            while i < len(pending) or waiting or preparing or resident:
                 now = time.monotonic() - t0
+                if self.progress_s > 0 and now - last_report >= self.progress_s:
+                    last_report = now
+                    print(f"[serve] t={now:.0f}s done={len(results)} resident={len(resident)} "
+                          f"preparing={len(preparing)} waiting={len(waiting)} pending={len(pending) - i}",
+                          file=sys.stderr, flush=True)
+                while i < len(pending) and pending[i].arrival <= now:
+                    waiting.append(pending[i])
+                    i += 1
+                # admission by slot and HBM footprint; preparation overlaps the GPU
+                while waiting and len(resident) + len(preparing) < self.max_slots:
+                    r = waiting[0]
+                    need = self._footprint(r.workload)
+                    if used + need > self.budget and (resident or preparing):
+                        break
+                    waiting.pop(0)
+                    used += need
+                    preparing.append([r, pool.submit(self._prepare, r), need, now])
+                # prepared runs join the batch
                 still = []
-                for rec in resident:
-                    r, sim, remaining, adm, nb = rec
-                    if remaining == 0:
-                        obs = sim.observe()
-                        state = None
-                        if self.keep_state:
-                            state = {"N": sim.read(lbm.FIELD_N_OFFSET), "B": sim.read(lbm.FIELD_B)}
-                        results.append(Result(r.rid, r.arrival, adm, time.monotonic() - t0, r.workload.nodes,
-                                              r.steps, obs, state))
-                        sim.close()
-                        del sim
-                        used -= nb
+                for rec in preparing:
+                    r, fut, need, adm = rec
+                    if fut.done():
+                        sim = fut.result()
+                        used += sim.device_bytes - need
+                        resident.append([r, sim, r.steps, adm, sim.device_bytes])
                     else:
                         still.append(rec)
-                resident = still
-                continue
-            if not resident:
-                if i < len(pending):
-                    time.sleep(max(0.0, min(0.05, pending[i].arrival - (time.monotonic() - t0))))
-                continue
-            self.init_stream.synchronize()
-            steps = [min(self.tick, rec[2]) for rec in resident]
-            self.batch.step([rec[1] for rec in resident], steps)
-            for rec, s in zip(resident, steps):
-                rec[2] -= s
-            busy = True
+                preparing = still
+                if busy:
+                    self.stream.synchronize()
+                    busy = False
+                    still = []
+                    for rec in resident:
+                        r, sim, remaining, adm, nb = rec
+                        if remaining == 0:
+                            obs = sim.observe()
+                            state = None
+                            if self.keep_state:
+                                state = {"N": sim.read(lbm.FIELD_N_OFFSET), "B": sim.read(lbm.FIELD_B)}
+                            results.append(Result(r.rid, r.arrival, adm, time.monotonic() - t0, r.workload.nodes,
+                                                  r.steps, obs, state))
+                            sim.close()
+                            del sim
+                            used -= nb
+                        else:
+                            still.append(rec)
+                    resident = still
+                    continue
+                if not resident:
+                    if preparing:
+                        wait([rec[1] for rec in preparing], timeout=0.05, return_when=FIRST_COMPLETED)
+                    elif i < len(pending):
+                        time.sleep(max(0.0, min(0.05, pending[i].arrival - (time.monotonic() - t0))))
+                    continue
+                self.init_stream.synchronize()
+                steps = [min(self.tick, rec[2]) for rec in resident]
+                self.batch.step([rec[1] for rec in resident], steps)
+                for rec, s in zip(resident, steps):
+                    rec[2] -= s
+                busy = True
+        finally:
+            pool.shutdown(wait=True)
         torch.cuda.synchronize(self.device)
         return sorted(results, key=lambda r: r.rid)
 
