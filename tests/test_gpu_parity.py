@@ -338,17 +338,25 @@ def test_runtime_argument_errors():
         sim.set_field(lbm.FIELD_PHI, bad)
 
 
-@pytest.mark.parametrize("wl", [W.cylinder_d2q9_128(theta=30.0), W.sphere_d3q19(32, theta=60.0, precision=W.FP32)],
-                         ids=["d2q9_f64", "d3q19_f32"])
-def test_step_graph_replays_equal_direct_launches(wl):
+@pytest.mark.parametrize("case", ["d2q9_f64", "d3q19_f32", "packing_sparse_f32"])
+def test_step_graph_replays_equal_direct_launches(case):
     """With LBM_OPT_GRAPH lbm_step replays a captured two-step HIP graph for
     long runs: every replay, with eager single steps, reads and
     synchronisations in between, matches the same run launched kernel by
-    kernel, bit for bit; a wetting change drops the graph and takes effect."""
+    kernel, bit for bit; a wetting change drops the graph and takes effect.
+    Also in the fluid-only layout."""
     lbm = _lbm()
+    extra = 0
+    if case == "d2q9_f64":
+        wl = W.cylinder_d2q9_128(theta=30.0)
+    elif case == "d3q19_f32":
+        wl = W.sphere_d3q19(32, theta=60.0, precision=W.FP32)
+    else:
+        wl = W.porous_d3q19(n=40, sphere_radius=5.0, porosity=0.40, seed=0, precision=W.FP32, front=10.0)
+        extra = lbm.OPT_SPARSE
     phi0 = W.initial_phi(wl)
-    a = lbm.Simulation(wl, phi0, options=8)         # graphs
-    b = lbm.Simulation(wl, phi0)                    # direct launches
+    a = lbm.Simulation(wl, phi0, options=lbm.OPT_GRAPH | extra)   # graphs
+    b = lbm.Simulation(wl, phi0, options=extra)                   # direct launches
     plan = [10, 1, 9, 16, 3, 12]
     for k, n in enumerate(plan):
         if k == 3:
