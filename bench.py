@@ -7,10 +7,18 @@ ratio 1000, viscosity ratio 100, FP32) with the state resident in HBM:
 colour field, ghost-node update, fused collide-stream.  Prints one JSON line:
 MLUPS (Eq. 14: box nodes x steps / (seconds x 1e6)), the roofline of the
 dominant kernel (fused collide-stream) from HIP events on the library's
-stream, and the FP64 CPU oracle timed on the host on a few steps of the same
-box.
+stream with its HBM traffic from the committed rocprofv3 counters, a short
+served mix (p50 / p99 latency, FP32 and FP16 storage), and the FP64 CPU
+oracle timed on the host on a few steps of the same box.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--size 256]
+           [--precision f32|f64|f16ofs|bf16ofs] [--workload sphere|porous]
+           [--layout box|sparse] [--no-serve] [--no-cpu-baseline]
+       python bench.py --cpu-windows     (oracle timings only, no GPU)
+       python bench.py --calibrate-copy  (plain 1 GiB copy, for counters)
+
+--workload porous runs the 384^3 sphere packing (theta 45, density ratio
+10, body force 1e-6) in the fluid-only storage layout by default.
 """
 from __future__ import annotations
 
