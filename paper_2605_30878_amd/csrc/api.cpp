@@ -49,6 +49,7 @@ struct lbm_ctx {
     std::vector<uint8_t> slot_flags;   // [M]
     std::vector<uint32_t> nbt;         // [Q - 1][n_fluid] slot of fluid slot k + c_i
     std::vector<double> stage;         // [M] host staging of one plane
+    std::vector<int32_t> up_node, up_corner;  // slot-mapped ghost list, alive until its upload completes
     int64_t step = 0;
     std::string err;
 };
@@ -597,16 +598,16 @@ int lbm_bind(lbm_ctx* c, void* dev, size_t bytes, void* stream) {
     d.sparse = c->sparse ? 1 : 0;
     // Upload the geometry (slot-indexed in the sparse layout).
     hipStream_t st = c->stream;
-    std::vector<int32_t> g_node_up, g_corner_up;
     const int32_t* g_node_src = c->g_node.data();
     const int32_t* g_corner_src = c->g_corner.data();
     if (c->sparse) {
-        g_node_up.resize(c->g_node.size());
-        g_corner_up.resize(c->g_corner.size());
-        for (size_t k = 0; k < g_node_up.size(); k++) g_node_up[k] = c->slot_of[c->g_node[k]];
-        for (size_t k = 0; k < g_corner_up.size(); k++) g_corner_up[k] = c->slot_of[c->g_corner[k]];
-        g_node_src = g_node_up.data();
-        g_corner_src = g_corner_up.data();
+        // kept in the context: an error return below may leave copies pending
+        c->up_node.resize(c->g_node.size());
+        c->up_corner.resize(c->g_corner.size());
+        for (size_t k = 0; k < c->up_node.size(); k++) c->up_node[k] = c->slot_of[c->g_node[k]];
+        for (size_t k = 0; k < c->up_corner.size(); k++) c->up_corner[k] = c->slot_of[c->g_corner[k]];
+        g_node_src = c->up_node.data();
+        g_corner_src = c->up_corner.data();
         HIPCHK(c, hipMemcpyAsync(d.flags, c->slot_flags.data(), (size_t)c->M, hipMemcpyHostToDevice, st),
                "upload flags");
         if (!c->nbt.empty())
@@ -635,6 +636,8 @@ int lbm_bind(lbm_ctx* c, void* dev, size_t bytes, void* stream) {
         }
     }
     HIPCHK(c, hipStreamSynchronize(st), "sync");
+    std::vector<int32_t>().swap(c->up_node);
+    std::vector<int32_t>().swap(c->up_corner);
     c->bound = true;
     return LBM_OK;
 }
