@@ -1235,6 +1235,38 @@ __global__ __launch_bounds__(256) void k_macro(const SN* __restrict__ Nsrc, cons
     aux[3 * S + x] = (double)m.p;
 }
 
+// Reduction of the seven diagnostics (six sums, the maximum at index 5) and
+// the non-finite count over a 256-thread block: a butterfly across the 64
+// lanes of each wave (__shfl_xor), then the four waves' results in order.
+// The order is fixed, so the result is deterministic; valid in thread 0.
+__device__ __forceinline__ void block_reduce_diag(double (&v)[7], int64_t& bad) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < 7; k++) {
+            const double o = __shfl_xor(v[k], off, 64);
+            v[k] = k == 5 ? (o > v[k] ? o : v[k]) : v[k] + o;
+        }
+        bad += (int64_t)__shfl_xor((long long)bad, off, 64);
+    }
+    __shared__ double wv[4][7];
+    __shared__ int64_t wn[4];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < 7; k++) wv[w][k] = v[k];
+        wn[w] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int j = 1; j < 4; j++) {
+#pragma unroll
+            for (int k = 0; k < 7; k++) v[k] = k == 5 ? (wv[j][k] > v[k] ? wv[j][k] : v[k]) : v[k] + wv[j][k];
+            bad += wn[j];
+        }
+    }
+}
+
 // Diagnostics, stage 1: each block reduces a fixed strided set of nodes in a
 // fixed order (deterministic for a fixed grid).  Values: sum phi,
 // sum (1 - phi), sum rho u (3), max |u|, sum rho |u|^2 / 2; non-finite count
@@ -1245,8 +1277,6 @@ __global__ __launch_bounds__(256) void k_reduce1(const SN* __restrict__ N, const
                                                  const double* __restrict__ aux, int64_t n, int64_t S, double rho_g,
                                                  double drho, double* __restrict__ partial,
                                                  int64_t* __restrict__ nonfinite) {
-    __shared__ double sh[7][256];
-    __shared__ int64_t shn[256];
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     int64_t bad = 0;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -1270,23 +1300,10 @@ __global__ __launch_bounds__(256) void k_reduce1(const SN* __restrict__ N, const
         for (int i = 0; i < nB; i++)
             if (!isfinite((double)Bstate[(int64_t)i * S + x])) bad++;
     }
-    const int t = threadIdx.x;
-    for (int k = 0; k < 7; k++) sh[k][t] = v[k];
-    shn[t] = bad;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (t < off) {
-            for (int k = 0; k < 7; k++) {
-                if (k == 5) sh[k][t] = sh[k][t] > sh[k][t + off] ? sh[k][t] : sh[k][t + off];
-                else sh[k][t] += sh[k][t + off];
-            }
-            shn[t] += shn[t + off];
-        }
-        __syncthreads();
-    }
-    if (t == 0) {
-        for (int k = 0; k < 7; k++) partial[(int64_t)blockIdx.x * 8 + k] = sh[k][0];
-        nonfinite[blockIdx.x] = shn[0];
+    block_reduce_diag(v, bad);
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 7; k++) partial[(int64_t)blockIdx.x * 8 + k] = v[k];
+        nonfinite[blockIdx.x] = bad;
     }
 }
 
@@ -1294,8 +1311,6 @@ __global__ __launch_bounds__(256) void k_reduce1(const SN* __restrict__ N, const
 __global__ __launch_bounds__(256) void k_reduce2(const double* __restrict__ partial,
                                                  const int64_t* __restrict__ nonfinite, int nblocks,
                                                  double* __restrict__ result, int64_t* __restrict__ nf_out) {
-    __shared__ double sh[7][256];
-    __shared__ int64_t shn[256];
     const int t = threadIdx.x;
     double v[7] = {0, 0, 0, 0, 0, 0, 0};
     int64_t bad = 0;
@@ -1307,22 +1322,10 @@ __global__ __launch_bounds__(256) void k_reduce2(const double* __restrict__ part
         }
         bad += nonfinite[b];
     }
-    for (int k = 0; k < 7; k++) sh[k][t] = v[k];
-    shn[t] = bad;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (t < off) {
-            for (int k = 0; k < 7; k++) {
-                if (k == 5) sh[k][t] = sh[k][t] > sh[k][t + off] ? sh[k][t] : sh[k][t + off];
-                else sh[k][t] += sh[k][t + off];
-            }
-            shn[t] += shn[t + off];
-        }
-        __syncthreads();
-    }
+    block_reduce_diag(v, bad);
     if (t == 0) {
-        for (int k = 0; k < 7; k++) result[k] = sh[k][0];
-        *nf_out = shn[0];
+        for (int k = 0; k < 7; k++) result[k] = v[k];
+        *nf_out = bad;
     }
 }
 
