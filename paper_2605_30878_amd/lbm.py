@@ -172,6 +172,7 @@ class Simulation:
         ptr = self.buffer.data_ptr()
         aligned = (ptr + 255) & ~255
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._streams = [self.stream]   # streams that may still run work on this run (batches add theirs)
         self._check(lib.lbm_bind(h, C.c_void_p(aligned), self.device_bytes, C.c_void_p(self.stream.cuda_stream)))
         self._check(lib.lbm_set_wetting(h, float(wl.theta)))
         if phi_init is None:
@@ -183,10 +184,16 @@ class Simulation:
             raise LbmError(rc, self.lib.lbm_last_error(self._h).decode())
 
     def close(self):
+        """Wait for the run's queued work, destroy the context and release
+        the device buffer (the caching allocator tracks only the stream the
+        buffer was allocated on, not the run's)."""
         h = getattr(self, "_h", None)
         if h is not None and h.value:
+            for stream in getattr(self, "_streams", []):
+                stream.synchronize()
             self.lib.lbm_destroy(h)
             self._h = None
+            self.buffer = None
 
     def __del__(self):
         try:
@@ -257,6 +264,9 @@ class Batch:
 
     def step(self, sims: Sequence["Simulation"], steps: Sequence[int]):
         n = len(sims)
+        for s in sims:
+            if all(t is not self.stream for t in s._streams):
+                s._streams.append(self.stream)
         arr = (C.c_void_p * max(n, 1))(*[s._h for s in sims])
         st = (C.c_int64 * max(n, 1))(*[int(k) for k in steps])
         rc = self.lib.lbm_batch_step(self._h, arr, st, n)
@@ -266,8 +276,10 @@ class Batch:
     def close(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
+            self.stream.synchronize()   # the job table is read by queued launches
             self.lib.lbm_batch_destroy(h)
             self._h = None
+            self.table = None
 
     def __del__(self):
         try:
