@@ -175,3 +175,68 @@ def test_sparse_option_combinations_and_bytes():
     slots = nf + ng + 1
     assert sizes[lbm.OPT_SPARSE] >= (3 * 19 + 2 * 4) * slots * 4 + 18 * nf * 4
     assert sizes[lbm.OPT_SPARSE] < sizes[0]
+
+
+def _valid(lattice, n, rho_l, rho_g, mu_l, mu_g, sigma, Wd, mob, g, options):
+    """The acceptance rules lbm_create documents, restated."""
+    import math
+    if lattice == W.D2Q9 and n[2] != 1:
+        return False
+    if min(n) < 1 or n[1] > 65535 or n[2] > 65535:
+        return False
+    if not (rho_l > 0 and rho_g > 0 and mu_l > 0 and mu_g > 0):
+        return False
+    if not sigma >= 0 or not Wd >= 4.0 or not mob > 0:
+        return False
+    if not all(math.isfinite(a) for a in g):
+        return False
+    if options & 32 and options & (1 | 4):
+        return False
+    cs2 = 1.0 / 3.0
+    w0 = 4.0 / 9 if lattice == W.D2Q9 else 1.0 / 3
+    alpha = 1.0 - 2.0 * mob * (1.0 - w0) / cs2
+    if not (alpha >= 0.0 and alpha < 1.0):
+        return False
+    return (0.5 + (mu_l / rho_l) / cs2 > 0.5) and (0.5 + (mu_g / rho_g) / cs2 > 0.5)
+
+
+def test_create_accepts_exactly_the_documented_parameters():
+    """Seeded random parameter sets, valid and not (zero, negative, NaN and
+    infinite values, small and large mobilities, option clashes): lbm_create
+    returns OK exactly when the documented rules hold, else LBM_EINVAL with a
+    message, and never crashes."""
+    lib = lbm.load_library()
+    rng = np.random.default_rng(7)
+    specials = [0.0, -1.0, float("nan"), float("inf"), 1e-300, 1e300]
+
+    def pick(lo, hi):
+        return specials[rng.integers(len(specials))] if rng.uniform() < 0.15 else float(rng.uniform(lo, hi))
+
+    seen = {True: 0, False: 0}
+    for _ in range(400):
+        lattice = int(rng.integers(2))
+        n = [int(rng.integers(0, 40)), int(rng.integers(0, 40)), 1 if lattice == W.D2Q9 else int(rng.integers(0, 40))]
+        if lattice == W.D2Q9 and rng.uniform() < 0.1:
+            n[2] = 2
+        vals = dict(rho_l=pick(0.5, 1000.0), rho_g=pick(0.5, 2.0), mu_l=pick(0.01, 10.0), mu_g=pick(0.01, 1.0),
+                    sigma=pick(0.0, 0.1), Wd=pick(3.0, 8.0), mob=pick(0.0, 0.4))
+        g = [pick(-1e-5, 1e-5) if rng.uniform() < 0.3 else 0.0 for _ in range(3)]
+        options = int(rng.integers(0, 64))
+        wl = W.Workload(name="p", lattice=lattice, shape=tuple(max(v, 1) for v in n), rho_l=vals["rho_l"],
+                        rho_g=vals["rho_g"], mu_l=vals["mu_l"], mu_g=vals["mu_g"], sigma=vals["sigma"],
+                        W=vals["Wd"], mobility=vals["mob"], g=tuple(g))
+        p = lbm.make_params(wl, options)
+        for a in range(3):
+            p.n[a] = n[a]
+        h = C.c_void_p()
+        rc = lib.lbm_create(C.byref(p), C.byref(h))
+        want = _valid(lattice, n, vals["rho_l"], vals["rho_g"], vals["mu_l"], vals["mu_g"], vals["sigma"], vals["Wd"],
+                      vals["mob"], g, options)
+        assert rc == (lbm.OK if want else lbm.EINVAL), (lattice, n, vals, g, options, rc)
+        if rc == lbm.OK:
+            assert h.value
+            assert lib.lbm_destroy(h) == lbm.OK
+        else:
+            assert not h.value and lib.lbm_last_error(None)
+        seen[want] += 1
+    assert seen[True] > 40 and seen[False] > 40
