@@ -240,3 +240,30 @@ def test_create_accepts_exactly_the_documented_parameters():
             assert not h.value and lib.lbm_last_error(None)
         seen[want] += 1
     assert seen[True] > 40 and seen[False] > 40
+
+
+def test_set_geometry_rejects_bad_solids():
+    """lbm_set_geometry's documented errors: a negative count or a null list,
+    an unknown kind, a ball wider than the box, a negative radius, a zero
+    half-space normal; a failed call leaves the context without geometry, so
+    a correct call still succeeds afterwards."""
+    lib = lbm.load_library()
+    wl = W.cylinder_d2q9_128()
+    bad = [
+        [W.Solid(2, (10.0, 10.0, 0.0), 3.0)],                          # unknown kind
+        [W.Solid(0, (64.0, 64.0, 0.0), 64.0)],                         # 2r = 128: not narrower than the box
+        [W.Solid(0, (64.0, 64.0, 0.0), -1.0)],                         # negative radius
+        [W.Solid(1, (0.0, 10.0, 0.0), normal=(0.0, 0.0, 0.0))],        # zero normal
+    ]
+    rc, h = _create(wl)
+    assert rc == lbm.OK
+    assert lib.lbm_set_geometry(h, lbm.make_solids(wl.solids), -1) == lbm.EINVAL
+    assert lib.lbm_set_geometry(h, None, 1) == lbm.EINVAL
+    for solids in bad:
+        assert lib.lbm_set_geometry(h, lbm.make_solids(solids), len(solids)) == lbm.EINVAL, solids
+        assert lib.lbm_last_error(h)
+    nbytes = C.c_size_t()
+    assert lib.lbm_device_bytes(h, C.byref(nbytes)) == lbm.ESTATE
+    assert lib.lbm_set_geometry(h, lbm.make_solids(wl.solids), len(wl.solids)) == lbm.OK
+    assert lib.lbm_device_bytes(h, C.byref(nbytes)) == lbm.OK
+    assert lib.lbm_destroy(h) == lbm.OK
