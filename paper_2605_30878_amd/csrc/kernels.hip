@@ -28,6 +28,17 @@
 // new ones, and the previous step's phi at fluid nodes stays available for
 // the compact B.  Every kernel is HBM-bound; nothing is a dense contraction,
 // so no MFMA is used.
+//
+// Launch forms of the colour and collide kernels (one set of per-node
+// functions, so every form computes the same values bit for bit):
+//   box planes, D3Q19 boxes tiled by 64 x 8: k_colour_tile (z-marching, the
+//     compact record of three planes and a one-node ring in LDS) and the
+//     row kernel k_collide_stream;
+//   box planes otherwise: the row kernels k_colour_compact, k_collide_stream;
+//   fluid-node list over box planes: k_colour_list, k_collide_list;
+//   fluid-only slots (packings): k_colour_sparse, k_collide_sparse;
+//   many runs at once: kb_colour, kb_ghost, kb_collide over a job table;
+//   fused one-launch D3Q19 step (opt-in): k_ghost_direct, k_step_fused.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
