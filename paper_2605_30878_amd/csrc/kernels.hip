@@ -72,6 +72,15 @@ template <class V>
 __device__ __forceinline__ V ld(const V* __restrict__ base, uint32_t idx) {
     return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(V));
 }
+// The same for a population plane that a launch streams through once:
+// a non-temporal load, so the streamed planes (far larger than the caches)
+// do not evict the colour field and compact record that the stencils and
+// gathers reuse (measured 1.6 % faster per step at 256^3, FP32 and FP16).
+template <class V>
+__device__ __forceinline__ V ld_nt(const V* __restrict__ base, uint32_t idx) {
+    return __builtin_nontemporal_load(
+        reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(V)));
+}
 template <class V>
 __device__ __forceinline__ void st(V* __restrict__ base, uint32_t idx, V v) {
     *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(V)) = v;
@@ -713,7 +722,7 @@ __global__ __launch_bounds__(CTX * CTY) void k_colour_tile(const SN* __restrict_
     SN nxt[19];
     colour_tile_fetch<T>(rec, z0 + 1, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
 #pragma unroll
-    for (int i = 0; i < 19; i++) raw[i] = ld(N + (int64_t)i * S, xy + plane * (uint32_t)z0);
+    for (int i = 0; i < 19; i++) raw[i] = ld_nt(N + (int64_t)i * S, xy + plane * (uint32_t)z0);
 #endif
     for (int z = z0; z < z1; z++) {
 #if LBM_COLOUR_PIPE
@@ -723,13 +732,13 @@ __global__ __launch_bounds__(CTX * CTY) void k_colour_tile(const SN* __restrict_
         __syncthreads();
         if (z + 1 < z1) {
 #pragma unroll
-            for (int i = 0; i < 19; i++) nxt[i] = ld(N + (int64_t)i * S, xy + plane * (uint32_t)(z + 1));
+            for (int i = 0; i < 19; i++) nxt[i] = ld_nt(N + (int64_t)i * S, xy + plane * (uint32_t)(z + 1));
         }
         colour_tile_fetch<T>(rec, z + 2, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
 #else
         // N of plane z, the record of plane z + AHEAD into LDS
 #pragma unroll
-        for (int i = 0; i < 19; i++) raw[i] = ld(N + (int64_t)i * S, xy + plane * (uint32_t)z);
+        for (int i = 0; i < 19; i++) raw[i] = ld_nt(N + (int64_t)i * S, xy + plane * (uint32_t)z);
         colour_tile_load<T>(sm, z + AHEAD, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
         __syncthreads();
 #endif
@@ -870,7 +879,7 @@ __global__ __launch_bounds__(CTX * CTY) void k_colour_tile_g(const SN* __restric
         // N of plane z; phi_prev of plane z + 2, p and flags of plane z + 1
         SN raw[19];
 #pragma unroll
-        for (int i = 0; i < 19; i++) raw[i] = ld(N + (int64_t)i * S, xy + plane * (uint32_t)z);
+        for (int i = 0; i < 19; i++) raw[i] = ld_nt(N + (int64_t)i * S, xy + plane * (uint32_t)z);
         colour_g_load_phi<T>(sm, z + 2, x0, y0, phi_prev, P.nx, P.ny, P.nz);
         colour_g_load_pf<T>(sm, z + 1, x0, y0, prec, flags, P.nx, P.ny, P.nz);
         __syncthreads();
@@ -1005,7 +1014,7 @@ __device__ __forceinline__ void collide_core(const SN* __restrict__ Nsrc, SN* __
     const int64_t S = P.S;
     T N[Q], ph[Q];
 #pragma unroll
-    for (int i = 0; i < Q; i++) N[i] = NS::dec(ld(Nsrc + (int64_t)i * S, x), P.n_s);
+    for (int i = 0; i < Q; i++) N[i] = NS::dec(ld_nt(Nsrc + (int64_t)i * S, x), P.n_s);
 #pragma unroll
     for (int i = 0; i < Q; i++) ph[i] = ld(phi, nb[i]);
     Macro<T> m;
