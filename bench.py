@@ -118,6 +118,31 @@ def cpu_windows(threads) -> list:
     return out
 
 
+def hbm_ceiling(gib: int = 4, repeats: int = 10) -> dict:
+    """What plain streaming kernels reach on this device (lbm_hbm_probe over
+    `gib` GiB): read-only, copy, and the colour kernel's pattern of 19 FP32
+    plane reads and one plane write; GB/s of bytes moved, each the average
+    launch after two untimed ones."""
+    import torch
+
+    from paper_2605_30878_amd import lbm
+
+    nbytes = gib << 30
+    src = torch.zeros(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda:0")
+    m = nbytes // 76                           # plane length of the 19-plane pattern
+    out = {"bytes": nbytes}
+    for name, kind, s, d, moved in (("read", lbm.PROBE_READ, src, dst, nbytes),
+                                    ("copy", lbm.PROBE_COPY, src, dst, 2 * nbytes),
+                                    ("planes19", lbm.PROBE_PLANES, src[: 19 * m], dst[:m], 80 * m)):
+        lbm.hbm_probe(kind, s, d, 2)
+        ms = lbm.hbm_probe(kind, s, d, repeats)
+        out[name + "_gbs"] = round(moved / (ms * 1e-3) / 1e9, 1)
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -138,6 +163,8 @@ def main() -> int:
                          "(default: sparse for the porous packing, box otherwise)")
     ap.add_argument("--full-mix", action="store_true",
                     help="served mix at full size: 256 requests, 2000-20000 steps each")
+    ap.add_argument("--hbm-probe", action="store_true",
+                    help="only run the HBM reference kernels (read, copy, 19-plane pattern) over 4 GiB")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (for HBM counter calibration)")
     ap.add_argument("--cpu-windows", action="store_true",
@@ -169,6 +196,10 @@ def main() -> int:
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"calibration_copy_bytes": src.numel() * 4, "launches": 5}), flush=True)
+        return 0
+
+    if args.hbm_probe:
+        print(json.dumps({"hbm_ceiling": hbm_ceiling()}), flush=True)
         return 0
 
     from paper_2605_30878_amd import lbm

@@ -285,6 +285,23 @@ int lbm_batch_destroy(lbm_batch* batch);
 /* Last error of a batch call ("" if none). */
 const char* lbm_batch_last_error(const lbm_batch* batch);
 
+/* ---------------------------------------------------------------- measurement
+ * HBM reference kernels, not part of the time step: the rates plain
+ * streaming kernels reach on this device, against which the lattice kernels'
+ * bandwidth is read (beside the published peak).  Enqueues `repeats` >= 1
+ * launches on hip_stream between two HIP events, waits for the last, and
+ * writes the average milliseconds per launch to *ms_out.
+ *   kind 0 (read):   every 16-byte vector of src_bytes of src is loaded once;
+ *                    dst needs 4 * 4096 bytes (never written for zeroed src)
+ *   kind 1 (copy):   dst (src_bytes) = src, 16-byte vectors
+ *   kind 2 (planes): src is 19 FP32 planes of n = src_bytes / 76 values,
+ *                    dst (n FP32) = their sum, one 4-byte load per lane and
+ *                    plane (the colour-field kernel's access pattern)
+ * src and dst are device pointers, 16-byte aligned, owned by the caller.
+ * Errors: LBM_EINVAL for a bad kind, size, alignment or repeats; LBM_EHIP. */
+int lbm_hbm_probe(int32_t kind, const void* src, void* dst, size_t src_bytes, int32_t repeats,
+                  void* hip_stream, double* ms_out);
+
 /* Release the context's host memory.  The device buffer stays the caller's. */
 int lbm_destroy(lbm_ctx* ctx);
 

@@ -72,6 +72,7 @@ def _load():
         lib.orc_scalars.argtypes = [C.c_void_p, dp]
         lib.orc_set_state.argtypes = [C.c_void_p, dp, dp, dp]
         lib.orc_set_theta.argtypes = [C.c_void_p, C.c_double]
+        lib.orc_set_variant.argtypes = [C.c_void_p, C.c_int, C.c_int]
         lib.orc_ghost_rule.restype = C.c_double
         lib.orc_ghost_rule.argtypes = [C.c_double, C.c_double, C.c_int]
         _lib = lib
@@ -219,6 +220,19 @@ class OracleSim:
         _load().orc_set_state(self._h, _dp(N) if N is not None else None,
                               _dp(B) if B is not None else None,
                               _dp(ps) if ps is not None else None)
+
+    VISC, SEG = 0, 1
+    VISC_PAPER, VISC_FLIPPED, VISC_DROPPED, VISC_NO_TAU_FACTOR = 0, 1, 2, 3
+    SEG_CLAMPED, SEG_LITERAL = 0, 1
+
+    def set_variant(self, which: int, value: int) -> None:
+        """Alternative reading or planted mistake of one term (orc_set_variant):
+        VISC: 0 Eq. A11 as read, 1 sign flipped, 2 left out, 3 without the
+        (tau - 1/2)/tau factor; SEG: 0 max(phi (1 - phi), 0), 1 the literal
+        factor of Eq. A12.  The non-zero VISC values are planted mistakes for
+        negative controls of the pins."""
+        if _load().orc_set_variant(self._h, int(which), int(value)) != 0:
+            raise ValueError("unknown variant")
 
     def set_theta(self, theta: float) -> None:
         if _load().orc_set_theta(self._h, float(theta)) != 0:

@@ -237,6 +237,13 @@ typedef struct {
     double* phi;           /* [n] working colour field of the current step */
     double* snap;          /* [n] snapshot for the Jacobi ghost update */
     long step;
+    /* Alternative readings and planted mistakes (orc_set_variant); all 0 is
+     * the oracle as it is meant.  visc: 0 Eq. A11 as read (R-visc), 1 its
+     * sign flipped, 2 F_visc left out, 3 without the (tau - 1/2)/tau factor
+     * (F_visc = -Pi_dev . grad rho).  seg: 0 READING R-seg (amplitude
+     * max(phi (1 - phi), 0)), 1 the literal factor phi (1 - phi) of Eq. A12.
+     * visc 1-3 exist only so that a test can show its pin fails on them. */
+    int visc_variant, seg_variant;
 } orc_sim;
 
 static inline long wrap(long v, long n) { v %= n; return v < 0 ? v + n : v; }
@@ -348,6 +355,9 @@ static void compute_macro(const orc_sim* s, const double* N, const double* phi_n
             double acc = 0.0;
             for (int b = 0; b < 3; b++) acc += strain[a][b] * grad_rho[b];
             m->Fv[a] = cs2 * 1.0 * (m->tau - 0.5) * acc;
+            if (s->visc_variant == 1) m->Fv[a] = -m->Fv[a];
+            else if (s->visc_variant == 2) m->Fv[a] = 0.0;
+            else if (s->visc_variant == 3) m->Fv[a] = cs2 * m->tau * acc;   /* = -Pi_dev . grad rho */
         }
     }
     /* Body force rho g (Eq. 2). */
@@ -413,7 +423,7 @@ static void collide_node(const orc_sim* s, const double* N, const double* phi_nb
     equilibrium(L, zero, m.p, neq0);
     double phi = m.phi;
     double amp = phi * (1.0 - phi);
-    if (amp < 0.0) amp = 0.0;
+    if (amp < 0.0 && s->seg_variant == 0) amp = 0.0;
     for (int i = 0; i < Q; i++) {
         double cn = L->c[i][0] * n[0] + L->c[i][1] * n[1] + L->c[i][2] * n[2];
         Bstar[i] = phi * Nstar[i] + 2.0 * cn / s->P.W * amp * neq0[i];
@@ -826,6 +836,16 @@ int orc_set_state(void* h, const double* N, const double* B, const double* phi_s
     if (N) memcpy(s->N, N, sizeof(double) * Q * n);
     if (B) memcpy(s->B, B, sizeof(double) * Q * n);
     if (phi_state) memcpy(s->phi_state, phi_state, sizeof(double) * n);
+    return 0;
+}
+
+/* Select an alternative reading or a planted mistake (see orc_sim):
+ * which 0 = visc (0..3), 1 = seg (0..1).  Returns -1 for an unknown one. */
+int orc_set_variant(void* h, int which, int value) {
+    orc_sim* s = (orc_sim*)h;
+    if (which == 0 && value >= 0 && value <= 3) s->visc_variant = value;
+    else if (which == 1 && value >= 0 && value <= 1) s->seg_variant = value;
+    else return -1;
     return 0;
 }
 

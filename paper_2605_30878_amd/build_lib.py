@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
-SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "api.cpp")]
+SOURCES = [os.path.join(CSRC, "kernels.hip"), os.path.join(CSRC, "api.cpp"), os.path.join(CSRC, "probe.hip")]
 HEADERS = [os.path.join(CSRC, "lattice.h"), os.path.join(CSRC, "launch.h"),
            os.path.join(os.path.dirname(HERE), "include", "lbm.h")]
 
@@ -32,7 +32,10 @@ FLAGS = [
 
 def build(verbose: bool = False, extra=None) -> str:
     tmp = LIB + f".tmp{os.getpid()}"
-    cmd = [HIPCC] + FLAGS + (extra or []) + ["-x", "hip", SOURCES[0], "-x", "hip", SOURCES[1], "-o", tmp]
+    srcs = []
+    for src in SOURCES:
+        srcs += ["-x", "hip", src]
+    cmd = [HIPCC] + FLAGS + (extra or []) + srcs + ["-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     out = "\n".join(l for l in (res.stdout + res.stderr).splitlines()
                     if "packed-fp32-ops" not in l and l.strip())

@@ -31,7 +31,7 @@ FLAG_SOLID, FLAG_NEAR_SOLID, FLAG_GHOST = 1, 2, 4
 EXPORTED = ["lbm_create", "lbm_set_geometry", "lbm_device_bytes", "lbm_bind", "lbm_set_wetting",
             "lbm_set_field", "lbm_step", "lbm_step_profiled", "lbm_observe", "lbm_read_field",
             "lbm_lattice", "lbm_destroy", "lbm_last_error", "lbm_batch_table_bytes", "lbm_batch_create",
-            "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_last_error"]
+            "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_last_error", "lbm_hbm_probe"]
 
 
 class LbmError(RuntimeError):
@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_batch_destroy.argtypes = [vp]
     lib.lbm_batch_last_error.argtypes = [vp]
     lib.lbm_batch_last_error.restype = C.c_char_p
+    lib.lbm_hbm_probe.argtypes = [C.c_int32, vp, vp, C.c_size_t, C.c_int32, vp, dp]
     for name in EXPORTED:
         if name not in ("lbm_last_error", "lbm_batch_last_error"):
             getattr(lib, name).restype = C.c_int
@@ -286,3 +287,23 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+PROBE_READ, PROBE_COPY, PROBE_PLANES = 0, 1, 2
+
+
+def hbm_probe(kind: int, src, dst, repeats: int = 10) -> float:
+    """Average milliseconds per launch of one HBM reference kernel
+    (lbm_hbm_probe) over `src` (all of it) into `dst`, both torch device
+    tensors, on torch's current stream."""
+    import torch
+
+    lib = load_library()
+    ms = np.zeros(1)
+    stream = torch.cuda.current_stream(src.device)
+    nbytes = src.numel() * src.element_size()
+    rc = lib.lbm_hbm_probe(int(kind), C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes,
+                           int(repeats), C.c_void_p(stream.cuda_stream), _dp(ms))
+    if rc != OK:
+        raise LbmError(rc, "lbm_hbm_probe failed")
+    return float(ms[0])

@@ -192,6 +192,29 @@ def apex_height(phi: np.ndarray, shape, x_line: Sequence[int], start: float, axi
     return float(last)
 
 
+def plate_angle_eq12(phi: np.ndarray, shape, wall: float = 0.5) -> dict:
+    """Contact angle of a 2D drop on the wall surface y = wall (solid rows
+    below it) by Eq. 12 (Sec. 3.1) with its spread S read as the half-base:
+    S is half the distance between the phi = 1/2 crossings on the first fluid
+    row, H the height of the last phi = 1/2 crossing above the wall on the
+    column through the drop's middle."""
+    nx, ny, _ = shape
+    f = phi.reshape(ny, nx)
+    row = f[1]
+    inside = np.flatnonzero(row > 0.5)
+    if inside.size == 0:
+        raise ValueError("drop does not touch the wall")
+    lo, hi = inside.min(), inside.max()
+    # linear interpolation of the two crossings on the first fluid row
+    xl = lo - (row[lo] - 0.5) / (row[lo] - row[lo - 1])
+    xr = hi + (row[hi] - 0.5) / (row[hi] - row[hi + 1])
+    S = 0.5 * (xr - xl)
+    xc = int(round(0.5 * (xl + xr)))
+    top = apex_height(phi, shape, (xc, 0, 0), 1.0, axis=1)
+    H = top - wall
+    return {"theta_eq12": plate_angle(S, H), "S": S, "H": H}
+
+
 def flat_contact_angle(phi: np.ndarray, shape, solid: np.ndarray, wall_y: float, W: float,
                        margin: float = 2.0) -> dict:
     """theta_m for a 2D cap on the wall surface y = wall_y: circle fit to the

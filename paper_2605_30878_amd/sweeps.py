@@ -63,20 +63,9 @@ def plate_case(theta: float, rule: int, nx: int = 500, ny: int = 300, area: floa
 
 def sphere_case(theta: float, n: int = 256, precision: int = W.FP32, probe: int = 0,
                 volume: float = None) -> W.Workload:
-    """The D3Q19 drop on a sphere of the benchmark box (sphere radius 48n/256
-    at the centre, density ratio 1000, viscosity ratio 100, W = 4), with the
-    drop started at its equilibrium cap for theta: the volume of the 40n/256
-    drop of the transient benchmark outside the sphere."""
-    s = n / 256.0
-    c = n / 2.0
-    R = 48.0 * s
-    if volume is None:
-        Rd = 40.0 * s
-        volume = 4.0 / 3.0 * math.pi * Rd ** 3 - measure.lens_volume(R, Rd, R)
-    Rc, d, _ = measure.drop_on_solid(R, volume, theta, 3)
-    return W.sphere_d3q19(n, theta=theta, precision=precision).with_(
-        name=f"sphere{n}_eq_t{theta:g}", probe=probe,
-        liquid=[W.LiquidRegion("ball", (c, c, c + d), Rc, width=4.0)])
+    """The benchmark box's drop on a sphere started at its equilibrium cap
+    for theta (`workloads.sphere_cap_d3q19`)."""
+    return W.sphere_cap_d3q19(n, theta=theta, precision=precision, probe=probe, volume=volume)
 
 
 def sphere_sweep(thetas=(30.0, 60.0, 90.0, 120.0, 150.0), n: int = 256, steps: int = 20000,
@@ -244,21 +233,7 @@ def cylinder_sweep(thetas=(30.0, 60.0, 90.0, 120.0, 150.0), rules=(0, 1), steps:
 
 
 def plate_angle_measured(phi: np.ndarray, shape, wall: float = 0.5) -> Dict[str, float]:
-    nx, ny, _ = shape
-    f = phi.reshape(ny, nx)
-    row = f[1]
-    inside = np.flatnonzero(row > 0.5)
-    if inside.size == 0:
-        raise ValueError("drop does not touch the wall")
-    lo, hi = inside.min(), inside.max()
-    # linear interpolation of the two crossings on the first fluid row
-    xl = lo - (row[lo] - 0.5) / (row[lo] - row[lo - 1])
-    xr = hi + (row[hi] - 0.5) / (row[hi] - row[hi + 1])
-    S = 0.5 * (xr - xl)
-    xc = int(round(0.5 * (xl + xr)))
-    top = measure.apex_height(phi, shape, (xc, 0, 0), 1.0, axis=1)
-    H = top - wall
-    return {"theta_eq12": measure.plate_angle(S, H), "S": S, "H": H}
+    return measure.plate_angle_eq12(phi, shape, wall)
 
 
 def plate_sweep(thetas=(30.0, 60.0, 90.0, 120.0, 150.0), rules=(0, 1), steps: int = 40000, Wd: float = 4.0,

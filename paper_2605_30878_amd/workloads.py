@@ -172,6 +172,29 @@ def sphere_d3q19(n: int = 256, theta: float = 90.0, precision: int = FP32,
         precision=precision, steps=steps)
 
 
+def sphere_cap_d3q19(n: int = 256, theta: float = 90.0, precision: int = FP32, probe: int = 0,
+                     volume: Optional[float] = None, steps: int = 20000) -> Workload:
+    """The drop on a sphere of `sphere_d3q19`, started at its equilibrium cap
+    for theta instead of the radius-40n/256 drop: a ball of radius R_c whose
+    centre is d above the sphere centre, with d^2 = R^2 + R_c^2 - 2 R R_c cos
+    theta (the drop meets the sphere at theta, Sec. 3.2) and R_c fixed by the
+    liquid volume outside the sphere.  The default volume is that of the
+    transient benchmark's drop outside the sphere.  The cap is geometry
+    (lens volumes of two balls), not a step of the method."""
+    from . import measure
+
+    s = n / 256.0
+    c = n / 2.0
+    R = 48.0 * s
+    if volume is None:
+        Rd = 40.0 * s
+        volume = 4.0 / 3.0 * math.pi * Rd ** 3 - measure.lens_volume(R, Rd, R)
+    Rc, d, _ = measure.drop_on_solid(R, volume, theta, 3)
+    return sphere_d3q19(n, theta=theta, precision=precision, steps=steps).with_(
+        name=f"sphere{n}_eq_t{theta:g}", probe=probe,
+        liquid=[LiquidRegion("ball", (c, c, c + d), Rc, width=4.0)])
+
+
 def free_drop(lattice: int, n: int, radius: float, rho_ratio: float = 1.0,
               mu_ratio: float = 1.0, W: float = 4.0, sigma: float = 0.01,
               precision: int = FP64) -> Workload:
