@@ -41,7 +41,7 @@
 extern "C" {
 #endif
 
-#define LBM_ABI_VERSION 1u
+#define LBM_ABI_VERSION 2u
 
 enum {
     LBM_OK = 0,
@@ -57,12 +57,20 @@ enum { LBM_D2Q9 = 0, LBM_D3Q19 = 1 };
 /* Population storage.  Arithmetic is FP64 for LBM_FP64 and FP32 otherwise. */
 enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_OFS = 2, LBM_BF16_OFS = 3 };
 
-/* Step forms.  By default every step is three launches: colour field,
- * ghost update, fused collide-stream.  With LBM_OPT_FUSED, D3Q19 boxes with
- * n[0] % 32 == 0, n[1] % 8 == 0 and n[2] >= 3 run each step (except the first
- * after an initial state or a restore) as a ghost pre-pass plus one launch
- * over 32 x 8 x z tiles that forms phi of the tile and a one-node ring in LDS
- * and reads N once.  Both compute the same update. */
+/* Step forms.  By default every step is three launches: colour field
+ * (phi = sum_i B_i, Eq. A13, from N and the compact record of the last
+ * collide), ghost update (Eq. 9), and the collide-stream kernel.  With
+ * LBM_OPT_FUSED, D3Q19 boxes with n[0] % 64 == 0 and n[1] % 8 == 0 run
+ * every step as the ghost update, one collide kernel over 64 x 8 columns
+ * that also forms the next step's phi from the recoloured populations it
+ * streams (Eq. A12, A17), and a small launch that adds the values crossing
+ * a column's faces.  N is then read once per step instead of twice, and no
+ * compact record is kept: after such a step the liquid state is phi itself,
+ * so lbm_read_field(LBM_FIELD_B) returns LBM_ESTATE; a checkpoint is N,
+ * LBM_FIELD_PHI_STATE and LBM_FIELD_SOLID_PHI.  Both forms compute the same update; N is bit-identical
+ * and phi differs only in the rounding order of the sum at nodes whose
+ * streamed-in populations cross a column face.  Other boxes, D2Q9 and
+ * LBM_OPT_SPARSE runs ignore the option for stepping. */
 #define LBM_OPT_FUSED 1
 
 /* Probe interpolation of the ghost rule.  By default phi_F at
@@ -79,15 +87,8 @@ enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_OFS = 2, LBM_BF16_OFS = 3 };
  * ratio 10, drives gas nodes there unstable within ~200 steps. */
 #define LBM_OPT_FLUID_PROBE 2
 
-/* Launch shape of the colour and collide kernels.  By default they launch
- * over the dense grid (solid nodes return at once).  LBM_OPT_FLUID_LIST
- * launches one thread per fluid node from a list kept in the device buffer
- * (measured slower on a 384^3 packing with 60 % solid nodes: the dense rows
- * keep every load coalesced).  Both compute the same update bit for bit. */
-#define LBM_OPT_FLUID_LIST 4
-
 /* With LBM_OPT_GRAPH, lbm_step with nsteps >= 8 replays a captured HIP graph
- * of two steps (six launches) after the first step of a run; the graph is
+ * of two steps after the first step of a run; the graph is
  * captured once per buffer parity on a private stream of default priority
  * and dropped by lbm_set_wetting and lbm_set_field.  Both forms compute the
  * same update bit for bit.  Off by default: on the paper's small D2Q9 boxes
@@ -113,8 +114,8 @@ enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_OFS = 2, LBM_BF16_OFS = 3 };
  * Q - 1 slot indices per fluid node (4 (Q - 1) bytes) gives each fluid
  * node's neighbours.  Launches cover the fluid slots only, and a step
  * computes the same values as the box layout, bit for bit.  Fields still
- * cross the ABI in box order.  Restrictions: it excludes LBM_OPT_FUSED and
- * LBM_OPT_FLUID_LIST (lbm_create returns LBM_EINVAL); such contexts step
+ * cross the ABI in box order.  Restrictions: it excludes LBM_OPT_FUSED
+ * (lbm_create returns LBM_EINVAL); such contexts step
  * only through lbm_step (lbm_batch_step returns LBM_EINVAL); setting
  * LBM_FIELD_SOLID_PHI needs one value for all non-ghost solid nodes
  * (LBM_EINVAL otherwise). */
@@ -130,16 +131,24 @@ enum {
                                  read: the phi (fluid and ghost nodes) the next
                                  step will use */
     LBM_FIELD_N = 1,          /* [Q][nodes] colour-blind populations (post-stream) */
-    LBM_FIELD_B = 2,          /* [Q][nodes] liquid populations (post-stream) */
+    LBM_FIELD_B = 2,          /* [Q][nodes] liquid populations (post-stream); not
+                                 readable after a collide-colour step (LBM_OPT_FUSED) */
     LBM_FIELD_U = 3,          /* [3][nodes] velocity u of Eq. A14 (read only) */
     LBM_FIELD_P = 4,          /* [nodes] auxiliary pressure p of Eq. A15 (read only) */
     LBM_FIELD_SOLID_PHI = 5,  /* [nodes] phi carried at solid nodes between steps */
     LBM_FIELD_FLAGS = 6,      /* [nodes] node class: 1 solid, 2 fluid next to a
                                  solid, 4 ghost (read only) */
-    LBM_FIELD_N_OFFSET = 7    /* [Q][nodes] N_i - chi_i as the library stores it
+    LBM_FIELD_N_OFFSET = 7,   /* [Q][nodes] N_i - chi_i as the library stores it
                                  (every precision keeps the offset from the
                                  rest state); exact in FP64 both ways, so a
                                  read-then-set checkpoint resumes bit for bit */
+    LBM_FIELD_PHI_STATE = 8   /* [nodes] read: as LBM_FIELD_PHI; set (after
+                                 LBM_FIELD_PHI): the fluid entries become the
+                                 colour field of the next step, which then
+                                 forms no colour field of its own.  With N
+                                 (or N_OFFSET) and SOLID_PHI it restores the
+                                 state of a run whose last step was
+                                 collide-colour (LBM_OPT_FUSED), bit for bit */
 };
 
 typedef struct lbm_ctx lbm_ctx;
@@ -153,9 +162,9 @@ typedef struct {
     uint32_t precision;     /* LBM_FP64 ... */
     uint32_t ghost_rule;    /* LBM_GHOST_EQ9 or LBM_GHOST_FAKHARI */
     int32_t n[3];           /* box nodes; n[2] must be 1 for D2Q9 */
-    int32_t options;        /* bit 0 (LBM_OPT_FUSED): use the fused one-launch D3Q19 step where it applies;
+    int32_t options;        /* bit 0 (LBM_OPT_FUSED): collide-colour D3Q19 steps where the box allows;
                                bit 1 (LBM_OPT_FLUID_PROBE): fluid-only probe interpolation;
-                               bit 2 (LBM_OPT_FLUID_LIST): fluid-list launches;
+                               bit 2: unused (LBM_EINVAL);
                                bit 3 (LBM_OPT_GRAPH): captured two-step graphs in lbm_step;
                                bit 4 (LBM_OPT_FILL_DEAD_ENDS): dead-end fluid nodes made solid;
                                bit 5 (LBM_OPT_SPARSE): fluid-only storage */
@@ -234,11 +243,13 @@ int lbm_set_field(lbm_ctx* ctx, int field, const double* host_src, size_t count)
 /* Enqueue nsteps >= 0 time steps on the bound stream; returns at once. */
 int lbm_step(lbm_ctx* ctx, int64_t nsteps);
 
-/* lbm_step with timing: brackets each of the three launches of every step
- * (0: colour field, 1: ghost update, 2: fused collide-stream) with HIP
- * events on the bound stream, waits for the last one, and writes the summed
- * milliseconds of each phase to ms_out[0..2] and the elapsed time from the
- * first to the last event to ms_out[3].  nsteps >= 1.  Synchronises. */
+/* lbm_step with timing: brackets each launch of every step (0: colour
+ * field, 1: ghost update, 2: collide-stream or collide-colour, 3: colour
+ * fix-up of the collide-colour form) with HIP events on the bound stream,
+ * waits for the last one, and writes the summed milliseconds of each phase
+ * to ms_out[0..3] and the elapsed time from the first to the last event to
+ * ms_out[4] (five doubles).  A phase a step does not launch reads ~0.
+ * nsteps >= 1.  Synchronises. */
 int lbm_step_profiled(lbm_ctx* ctx, int64_t nsteps, double* ms_out);
 
 /* Reduce the diagnostics on the device and copy them out (synchronises).

@@ -28,7 +28,6 @@ struct lbm_ctx {
     std::vector<int32_t> g_node, g_corner;  // corner: [NC][ng]
     std::vector<double> g_w;                // [NC][ng]
     std::vector<uint8_t> g_mask;
-    std::vector<int32_t> fluid;             // fluid node ids, ascending
     int64_t n_solid = 0;
     size_t need = 0;
     char* base = nullptr;
@@ -36,8 +35,7 @@ struct lbm_ctx {
     DevState d{};
     int cur = 0;   // population / compact-record buffer holding the state
     int ps = 0;    // phi buffer holding the solid values of the state
-    int from_planes = 1;  // liquid state in the B plane buffer (initial state, restore)
-    bool g_stale = false; // G planes of the record left unwritten by the last steps
+    int liq = LIQ_PLANES; // liquid state entering the next step (Liquid)
     hipStream_t cap_stream = nullptr;               // private stream for graph capture
     hipGraphExec_t graph2[2] = {nullptr, nullptr};  // two-step graphs, by buffer parity
     // Fluid-only layout (LBM_OPT_SPARSE): slots are the fluid nodes, the
@@ -53,11 +51,6 @@ struct lbm_ctx {
     int64_t step = 0;
     std::string err;
 };
-
-// Fluid slot order of the sparse layout: 0 = box order, b > 0 = b^3 bricks.
-#ifndef LBM_SPARSE_BRICK
-#define LBM_SPARSE_BRICK 0
-#endif
 
 static thread_local std::string g_create_error;
 
@@ -91,6 +84,13 @@ static void lattice_table(int lattice, int& D, int& Q, int& NC, const int (**c)[
 static size_t elem_size(uint32_t prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 2); }
 static size_t phi_size(uint32_t prec) { return prec == LBM_FP64 ? 8 : 4; }
 static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Device bytes of the collide-colour inbox of this run (0 unless its steps
+// take the collide-colour form).
+static size_t fused_cross_bytes(const lbm_ctx* c) {
+    if (!(c->P.options & LBM_OPT_FUSED) || c->sparse) return 0;
+    return cross_bytes((int)c->P.lattice, c->P.precision, c->sp);
+}
 
 extern "C" {
 
@@ -130,9 +130,11 @@ static hipGraphExec_t two_step_graph(lbm_ctx* c) {
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
-        hipError_t e1 = launch_step((int)c->P.lattice, c->P.precision, c->d, c->sp, c->cur, c->ps, 0, c->cap_stream);
+        // both steps enter in the state the run's own steps leave
+        const int liq = step_fused((int)c->P.lattice, c->d, c->sp) ? LIQ_PHI : LIQ_RECORD;
+        hipError_t e1 = launch_step((int)c->P.lattice, c->P.precision, c->d, c->sp, c->cur, c->ps, liq, c->cap_stream);
         hipError_t e2 = e1 == hipSuccess ? launch_step((int)c->P.lattice, c->P.precision, c->d, c->sp, c->cur ^ 1,
-                                                       c->ps ^ 1, 0, c->cap_stream)
+                                                       c->ps ^ 1, liq, c->cap_stream)
                                          : e1;
         e = hipStreamEndCapture(c->cap_stream, &g);
         if (e == hipSuccess) e = e2;
@@ -144,15 +146,6 @@ static hipGraphExec_t two_step_graph(lbm_ctx* c) {
         ge = nullptr;
     }
     return ge;
-}
-
-// Re-form the G planes of the compact record where the last single-run
-// steps left them unwritten, before a kernel that reads them.
-static hipError_t ensure_g(lbm_ctx* c) {
-    if (!c->g_stale) return hipSuccess;
-    c->g_stale = false;
-    if (c->from_planes) return hipSuccess;
-    return launch_g_record((int)c->P.lattice, c->P.precision, c->d, c->sp, c->cur, c->ps, c->stream);
 }
 
 int lbm_create(const lbm_params* P, lbm_ctx** out) {
@@ -174,8 +167,10 @@ int lbm_create(const lbm_params* P, lbm_ctx** out) {
     if (!(P->mobility > 0)) return fail(nullptr, LBM_EINVAL, "mobility must be > 0");
     for (int a = 0; a < 3; a++)
         if (!std::isfinite(P->body_accel[a])) return fail(nullptr, LBM_EINVAL, "body_accel not finite");
-    if ((P->options & LBM_OPT_SPARSE) && (P->options & (LBM_OPT_FUSED | LBM_OPT_FLUID_LIST)))
-        return fail(nullptr, LBM_EINVAL, "LBM_OPT_SPARSE excludes LBM_OPT_FUSED and LBM_OPT_FLUID_LIST");
+    const int32_t known = LBM_OPT_FUSED | LBM_OPT_FLUID_PROBE | LBM_OPT_GRAPH | LBM_OPT_FILL_DEAD_ENDS | LBM_OPT_SPARSE;
+    if (P->options & ~known) return fail(nullptr, LBM_EINVAL, "unknown option bits");
+    if ((P->options & LBM_OPT_SPARSE) && (P->options & LBM_OPT_FUSED))
+        return fail(nullptr, LBM_EINVAL, "LBM_OPT_SPARSE excludes LBM_OPT_FUSED");
 
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
     if (!c) return fail(nullptr, LBM_ENOMEM, "host allocation failed");
@@ -486,19 +481,10 @@ int lbm_set_geometry(lbm_ctx* c, const lbm_solid* solids, int32_t count) {
             c->node_of[k] = (int32_t)id;
             k++;
         };
-        if (LBM_SPARSE_BRICK > 0) {
-            // fluid slots brick by brick (bricks and the nodes in a brick
-            // in box order), so that most neighbours share a brick
-            const int64_t b = LBM_SPARSE_BRICK, bzs = D == 3 ? b : 1;
-            for (int64_t z0 = 0; z0 < nz; z0 += bzs)
-                for (int64_t y0 = 0; y0 < ny; y0 += b)
-                    for (int64_t x0 = 0; x0 < nx; x0 += b)
-                        for (int64_t z = z0; z < std::min<int64_t>(z0 + bzs, nz); z++)
-                            for (int64_t y = y0; y < std::min<int64_t>(y0 + b, ny); y++)
-                                for (int64_t x = x0; x < std::min<int64_t>(x0 + b, nx); x++) take(id_of(x, y, z));
-        } else {
-            for (int64_t id = 0; id < n; id++) take(id);
-        }
+        // fluid slots in box order: the +-x neighbours are adjacent slots
+        // and the +-y neighbours contiguous runs (numbering them brick by
+        // brick measured slower)
+        for (int64_t id = 0; id < n; id++) take(id);
         for (int64_t g = 0; g < ng; g++) {
             c->slot_of[ghosts[g]] = (int32_t)(nf + g);
             c->node_of[nf + g] = (int32_t)ghosts[g];
@@ -531,13 +517,8 @@ int lbm_set_geometry(lbm_ctx* c, const lbm_solid* solids, int32_t count) {
     off += align256((size_t)ng * NC * 4);               // g_corner
     off += align256((size_t)ng * NC * fs);              // g_w
     off += align256((size_t)ng);                        // g_mask
-    c->fluid.clear();
-    c->fluid.reserve((size_t)(n - c->n_solid));
-    for (int64_t id = 0; id < n; id++)
-        if (!(c->flags[id] & FLAG_SOLID)) c->fluid.push_back((int32_t)id);
-    if (c->sparse) std::vector<int32_t>().swap(c->fluid);
-    off += align256(c->fluid.size() * 4);               // fluid list
     off += align256(c->nbt.size() * 4);                 // neighbour slots (sparse layout)
+    off += align256(fused_cross_bytes(c));              // collide-colour inbox
     off += 4 * align256((size_t)c->S * 8);              // aux
     off += align256((size_t)REDUCE_BLOCKS * 8 * 8);     // partial
     off += align256(8 * 8);                             // result
@@ -583,18 +564,15 @@ int lbm_bind(lbm_ctx* c, void* dev, size_t bytes, void* stream) {
     d.g_corner = (int32_t*)p; p += align256((size_t)ng * NC * 4);
     d.g_w = p; p += align256((size_t)ng * NC * fs);
     d.g_mask = (uint8_t*)p; p += align256((size_t)ng);
-    d.fluid = (int32_t*)p; p += align256(c->fluid.size() * 4);
     d.nbt = (uint32_t*)p; p += align256(c->nbt.size() * 4);
+    d.cross = p; p += align256(fused_cross_bytes(c));
     d.aux = (double*)p; p += 4 * align256((size_t)c->S * 8);
     d.partial = (double*)p; p += align256((size_t)REDUCE_BLOCKS * 8 * 8);
     d.result = (double*)p; p += align256(8 * 8);
     d.nonfinite = (int64_t*)p; p += align256((size_t)(REDUCE_BLOCKS + 1) * 8);
     d.n_ghost = (int32_t)ng;
-    d.fused = (c->P.options & LBM_OPT_FUSED) ? 1 : 0;
-    d.n_fluid = c->sparse ? c->n - c->n_solid : (int64_t)c->fluid.size();
-    // Fluid-list launches (opt-in: on a 60 %-solid packing they measured
-    // slower than the dense grid, whose rows keep the loads coalesced).
-    d.list = (c->P.options & LBM_OPT_FLUID_LIST) ? 1 : 0;
+    d.fused = fused_cross_bytes(c) > 0 ? 1 : 0;
+    d.n_fluid = c->n - c->n_solid;
     d.sparse = c->sparse ? 1 : 0;
     // Upload the geometry (slot-indexed in the sparse layout).
     hipStream_t st = c->stream;
@@ -616,9 +594,6 @@ int lbm_bind(lbm_ctx* c, void* dev, size_t bytes, void* stream) {
     } else {
         HIPCHK(c, hipMemcpyAsync(d.flags, c->flags.data(), (size_t)c->n, hipMemcpyHostToDevice, st), "upload flags");
     }
-    if (!c->fluid.empty())   // box layout only (the sparse layout keeps no list)
-        HIPCHK(c, hipMemcpyAsync(d.fluid, c->fluid.data(), c->fluid.size() * 4, hipMemcpyHostToDevice, st),
-               "upload fluid list");
     if (ng > 0) {
         HIPCHK(c, hipMemcpyAsync(d.g_node, g_node_src, (size_t)ng * 4, hipMemcpyHostToDevice, st), "upload ghosts");
         HIPCHK(c, hipMemcpyAsync(d.g_corner, g_corner_src, (size_t)ng * NC * 4, hipMemcpyHostToDevice, st),
@@ -718,8 +693,7 @@ int lbm_set_field(lbm_ctx* c, int field, const double* src, size_t count) {
         if ((rc = upload_aux(c, src, n, 0)) != LBM_OK) return rc;
         HIPCHK(c, launch_init(lat, prec, c->d, c->sp, c->cur, c->ps, c->stream), "init");
         HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
-        c->from_planes = 1;
-        c->g_stale = false;
+        c->liq = LIQ_PLANES;
         c->step = 0;
         c->started = true;
         return LBM_OK;
@@ -728,22 +702,35 @@ int lbm_set_field(lbm_ctx* c, int field, const double* src, size_t count) {
     case LBM_FIELD_B:
         if (!c->started) return fail(c, LBM_ESTATE, "set PHI first");
         if (count != (size_t)c->Q * n) return fail(c, LBM_EINVAL, "N/B need Q*n values");
-        if (!c->from_planes) {
+        if (c->liq == LIQ_RECORD) {
             // The compact liquid record depends on N: write B out to the
             // plane buffer first so that it keeps its value.
-            HIPCHK(c, ensure_g(c), "G record");
             for (int i = 0; i < c->Q; i++) {
-                HIPCHK(c, launch_plane_out(lat, prec, c->d, c->sp, 1, i, c->cur, c->ps, 0, c->stream), "B out");
+                HIPCHK(c, launch_plane_out(lat, prec, c->d, c->sp, 1, i, c->cur, c->ps, LIQ_RECORD, c->stream),
+                       "B out");
                 HIPCHK(c, launch_plane_in(lat, prec, c->d, c->sp, 1, i, c->cur, c->stream), "B in");
             }
-            c->from_planes = 1;
+            c->liq = LIQ_PLANES;
         }
+        // In LIQ_PHI the liquid state is phi itself, which N does not change;
+        // setting B replaces it by the B planes.
+        if (field == LBM_FIELD_B) c->liq = LIQ_PLANES;
         for (int i = 0; i < c->Q; i++) {
             if ((rc = upload_aux(c, src + (size_t)i * n, n, 0)) != LBM_OK) return rc;
             HIPCHK(c, launch_plane_in(lat, prec, c->d, c->sp, n_plane_kind(field), i, c->cur, c->stream),
                    "plane in");
         }
         HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
+        return LBM_OK;
+    case LBM_FIELD_PHI_STATE:
+        // the colour field of the next step at fluid nodes becomes the
+        // liquid state (restore of a run whose last step was collide-colour)
+        if (!c->started) return fail(c, LBM_ESTATE, "set PHI first");
+        if (count != (size_t)n) return fail(c, LBM_EINVAL, "PHI_STATE needs n values");
+        if ((rc = upload_aux(c, src, n, 0)) != LBM_OK) return rc;
+        HIPCHK(c, launch_plane_in(lat, prec, c->d, c->sp, 4, 1 - c->ps, c->cur, c->stream), "plane in");
+        HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
+        c->liq = LIQ_PHI;
         return LBM_OK;
     case LBM_FIELD_SOLID_PHI:
         if (!c->started) return fail(c, LBM_ESTATE, "set PHI first");
@@ -761,11 +748,11 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
     if (!c) return LBM_EINVAL;
     if (!c->started) return fail(c, LBM_ESTATE, "set PHI before stepping");
     if (nsteps < 0) return fail(c, LBM_EINVAL, "nsteps must be >= 0");
-    const bool leaves_g = steps_leave_g((int)c->P.lattice, c->d, c->sp);
+    const int after = step_fused((int)c->P.lattice, c->d, c->sp) ? LIQ_PHI : LIQ_RECORD;
     // With LBM_OPT_GRAPH, long runs replay a captured two-step graph (one
     // launch per two steps instead of six) after the first step of a run.
     if ((c->P.options & LBM_OPT_GRAPH) && nsteps >= 8) {
-        if (c->from_planes) {
+        if (c->liq != after) {
             int rc = lbm_step(c, 1);
             if (rc != LBM_OK) return rc;
             nsteps--;
@@ -778,18 +765,15 @@ int lbm_step(lbm_ctx* c, int64_t nsteps) {
                 if (e != hipSuccess) return hip_fail(c, e, "graph launch");
             }
             c->step += 2 * pairs;
-            if (leaves_g) c->g_stale = true;
             nsteps -= 2 * pairs;
         }
     }
     for (int64_t k = 0; k < nsteps; k++) {
-        hipError_t e = launch_step((int)c->P.lattice, c->P.precision, c->d, c->sp, c->cur, c->ps, c->from_planes,
-                                   c->stream);
+        hipError_t e = launch_step((int)c->P.lattice, c->P.precision, c->d, c->sp, c->cur, c->ps, c->liq, c->stream);
         if (e != hipSuccess) return hip_fail(c, e, "step launch");
-        if (leaves_g) c->g_stale = true;
         c->cur ^= 1;
         c->ps ^= 1;
-        c->from_planes = 0;
+        c->liq = after;
         c->step++;
     }
     return LBM_OK;
@@ -799,7 +783,8 @@ int lbm_step_profiled(lbm_ctx* c, int64_t nsteps, double* ms_out) {
     if (!c || !ms_out) return LBM_EINVAL;
     if (!c->started) return fail(c, LBM_ESTATE, "set PHI before stepping");
     if (nsteps < 1) return fail(c, LBM_EINVAL, "nsteps must be >= 1");
-    const int NPH = 3;
+    const int NPH = STEP_PHASES;
+    const int after = step_fused((int)c->P.lattice, c->d, c->sp) ? LIQ_PHI : LIQ_RECORD;
     std::vector<hipEvent_t> ev((size_t)nsteps * (NPH + 1), nullptr);
     int rc = LBM_OK;
     for (size_t k = 0; k < ev.size(); k++) {
@@ -810,15 +795,13 @@ int lbm_step_profiled(lbm_ctx* c, int64_t nsteps, double* ms_out) {
         hipEvent_t* E = &ev[(size_t)s * (NPH + 1)];
         hipError_t e = hipEventRecord(E[0], c->stream);
         for (int ph = 0; ph < NPH && e == hipSuccess; ph++) {
-            e = launch_phase((int)c->P.lattice, c->P.precision, ph, c->d, c->sp, c->cur, c->ps, c->from_planes,
-                             c->stream);
+            e = launch_phase((int)c->P.lattice, c->P.precision, ph, c->d, c->sp, c->cur, c->ps, c->liq, c->stream);
             if (e == hipSuccess) e = hipEventRecord(E[ph + 1], c->stream);
         }
         if (e != hipSuccess) { rc = hip_fail(c, e, "profiled step"); break; }
-        if (steps_leave_g((int)c->P.lattice, c->d, c->sp)) c->g_stale = true;
         c->cur ^= 1;
         c->ps ^= 1;
-        c->from_planes = 0;
+        c->liq = after;
         c->step++;
     }
     if (rc == LBM_OK) {
@@ -826,7 +809,7 @@ int lbm_step_profiled(lbm_ctx* c, int64_t nsteps, double* ms_out) {
         if (e != hipSuccess) rc = hip_fail(c, e, "event sync");
     }
     if (rc == LBM_OK) {
-        double tot[NPH + 1] = {0, 0, 0, 0};
+        double tot[NPH + 1] = {};
         for (int64_t s = 0; s < nsteps && rc == LBM_OK; s++) {
             hipEvent_t* E = &ev[(size_t)s * (NPH + 1)];
             for (int ph = 0; ph < NPH; ph++) {
@@ -852,9 +835,10 @@ int lbm_observe(lbm_ctx* c, lbm_obs* out) {
     if (!c->started) return fail(c, LBM_ESTATE, "set PHI before observing");
     const int lat = (int)c->P.lattice;
     const uint32_t prec = c->P.precision;
-    HIPCHK(c, launch_colour(lat, prec, c->d, c->sp, c->cur, c->ps, c->from_planes, c->stream), "colour");
+    HIPCHK(c, launch_colour(lat, prec, c->d, c->sp, c->cur, c->ps, c->liq, c->stream), "colour");
     HIPCHK(c, launch_macro(lat, prec, c->d, c->sp, c->cur, c->ps, c->stream), "macro");
-    HIPCHK(c, launch_reduce(lat, prec, c->d, c->sp, c->cur, c->ps, c->from_planes, c->stream), "reduce");
+    const ReduceScratch rs{c->d.partial, c->d.nonfinite, c->d.result};
+    HIPCHK(c, launch_reduce(lat, prec, c->d, c->sp, c->cur, c->ps, c->liq, rs, c->stream), "reduce");
     double r[8];
     int64_t nf = 0;
     HIPCHK(c, hipMemcpyAsync(r, c->d.result, 8 * 8, hipMemcpyDeviceToHost, c->stream), "download");
@@ -908,20 +892,21 @@ int lbm_read_field(lbm_ctx* c, int field, double* dst, size_t count) {
     int rc;
     switch (field) {
     case LBM_FIELD_PHI:
+    case LBM_FIELD_PHI_STATE:
         if (count != (size_t)n) return fail(c, LBM_EINVAL, "PHI has n values");
-        HIPCHK(c, launch_colour(lat, prec, c->d, c->sp, c->cur, c->ps, c->from_planes, c->stream), "colour");
-        HIPCHK(c, launch_plane_out(lat, prec, c->d, c->sp, 2, 1 - c->ps, c->cur, c->ps, c->from_planes, c->stream),
+        HIPCHK(c, launch_colour(lat, prec, c->d, c->sp, c->cur, c->ps, c->liq, c->stream), "colour");
+        HIPCHK(c, launch_plane_out(lat, prec, c->d, c->sp, 2, 1 - c->ps, c->cur, c->ps, c->liq, c->stream),
                "plane out");
         return download(c, dst, c->d.aux, n);
     case LBM_FIELD_SOLID_PHI:
         if (count != (size_t)n) return fail(c, LBM_EINVAL, "SOLID_PHI has n values");
-        HIPCHK(c, launch_plane_out(lat, prec, c->d, c->sp, 2, c->ps, c->cur, c->ps, c->from_planes, c->stream),
+        HIPCHK(c, launch_plane_out(lat, prec, c->d, c->sp, 2, c->ps, c->cur, c->ps, c->liq, c->stream),
                "plane out");
         return download(c, dst, c->d.aux, n);
     case LBM_FIELD_U:
     case LBM_FIELD_P:
         if (count != (size_t)(field == LBM_FIELD_U ? 3 * n : n)) return fail(c, LBM_EINVAL, "wrong count");
-        HIPCHK(c, launch_colour(lat, prec, c->d, c->sp, c->cur, c->ps, c->from_planes, c->stream), "colour");
+        HIPCHK(c, launch_colour(lat, prec, c->d, c->sp, c->cur, c->ps, c->liq, c->stream), "colour");
         HIPCHK(c, launch_macro(lat, prec, c->d, c->sp, c->cur, c->ps, c->stream), "macro");
         if (field == LBM_FIELD_P) return download(c, dst, c->d.aux + 3 * c->S, n);
         for (int a = 0; a < 3; a++)
@@ -931,10 +916,12 @@ int lbm_read_field(lbm_ctx* c, int field, double* dst, size_t count) {
     case LBM_FIELD_N_OFFSET:
     case LBM_FIELD_B:
         if (count != (size_t)c->Q * n) return fail(c, LBM_EINVAL, "N/B have Q*n values");
-        if (field == LBM_FIELD_B) HIPCHK(c, ensure_g(c), "G record");
+        if (field == LBM_FIELD_B && c->liq == LIQ_PHI)
+            return fail(c, LBM_ESTATE,
+                        "the collide-colour step keeps phi, not B: read B after a step without LBM_OPT_FUSED");
         for (int i = 0; i < c->Q; i++) {
             HIPCHK(c, launch_plane_out(lat, prec, c->d, c->sp, n_plane_kind(field), i, c->cur, c->ps,
-                                       c->from_planes, c->stream),
+                                       c->liq, c->stream),
                    "plane out");
             if ((rc = download(c, dst + (size_t)i * n, c->d.aux, n)) != LBM_OK) return rc;
         }
@@ -992,15 +979,6 @@ int lbm_batch_step(lbm_batch* b, lbm_ctx* const* ctxs, const int64_t* steps, int
         for (int32_t k = 0; k < j; k++)
             if (ctxs[k] == ctxs[j]) return bfail(b, LBM_EINVAL, "a context appears twice");
     }
-    // Runs whose last single-run steps left the G planes of their record
-    // unwritten get them re-formed first (the batched colour kernel reads them).
-    for (int32_t j = 0; j < count; j++) {
-        lbm_ctx* c = ctxs[j];
-        if (!c->g_stale || steps[j] == 0) continue;
-        hipError_t eg = ensure_g(c);
-        if (eg == hipSuccess && c->stream != b->stream) eg = hipStreamSynchronize(c->stream);
-        if (eg != hipSuccess) return bfail(b, LBM_EHIP, std::string("G record: ") + hipGetErrorString(eg));
-    }
     // The staging buffers of the previous call must have reached the device.
     hipError_t e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) return bfail(b, LBM_EHIP, std::string("sync: ") + hipGetErrorString(e));
@@ -1018,7 +996,7 @@ int lbm_batch_step(lbm_batch* b, lbm_ctx* const* ctxs, const int64_t* steps, int
                 h.p = c->sp;
                 h.cur0 = c->cur;
                 h.ps0 = c->ps;
-                h.planes0 = c->from_planes;
+                h.planes0 = c->liq;
                 h.steps = steps[j];
                 jobs.push_back(h);
                 who.push_back(c);
@@ -1048,8 +1026,7 @@ int lbm_batch_step(lbm_batch* b, lbm_ctx* const* ctxs, const int64_t* steps, int
                     c->cur ^= 1;
                     c->ps ^= 1;
                 }
-                c->from_planes = 0;
-                c->g_stale = false;   // the batched collide writes the whole record
+                c->liq = LIQ_RECORD;   // the batched collide writes the compact record
                 c->step += n;
             }
         }

@@ -578,14 +578,9 @@ __global__ __launch_bounds__(256) void k_colour_compact(const SN* __restrict__ N
 #define LBM_CT_BLOCKS 2048
 #endif
 constexpr int CTX = LBM_CTX, CTY = LBM_CTY;        // tile
-// Record planes held in LDS: 3 (load one plane ahead, two barriers per
-// plane) or 5 (load two planes ahead, one barrier per plane; 69 KB of LDS
-// in FP32, measured slightly slower: 401 against 395 us at 256^3).
-#ifndef LBM_COLOUR_SLOTS
-#define LBM_COLOUR_SLOTS 3
-#endif
-constexpr int CSL = LBM_COLOUR_SLOTS;
-static_assert(CSL == 3 || CSL == 5, "three or five record planes");
+// Three record planes in LDS: the plane below, this one and the one above
+// (loaded one plane ahead; two barriers per plane).
+constexpr int CSL = 3;
 __device__ __forceinline__ int slotc(int z) { return (z % CSL + CSL) % CSL; }
 constexpr int CRX = CTX + 2, CRY = CTY + 2;       // tile + ring
 
@@ -596,7 +591,6 @@ struct ColourSmem {
 };
 
 __device__ __forceinline__ int wrapc(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
-__device__ __forceinline__ int slot3(int z) { return (z % 3 + 3) % 3; }
 
 // Tile schedule over a 1-D grid: XCD k (blocks with id % 8 == k) takes the
 // y-band [k yb, (k + 1) yb) of tiles when band > 0, x-tiles fastest, then
@@ -621,47 +615,8 @@ __device__ __forceinline__ void tile_index(const TileSched& s, int& bx, int& by,
     }
 }
 
-// LBM_COLOUR_PIPE=1 issues the loads of the next plane before the current
-// plane's arithmetic; it needs ~50 more VGPRs (two waves per SIMD fewer) and
-// measured slower at 256^3 (FP32 446 against 395 us, FP16 419 against 282).
-#ifndef LBM_COLOUR_PIPE
-#define LBM_COLOUR_PIPE 0
-#endif
-static_assert(!LBM_COLOUR_PIPE || CSL == 3, "the pipelined form keeps three record planes");
-
-// The record and flags of plane z for the tile and its ring, staged through
-// registers: each thread fetches up to two of the CRX * CRY entries (one
-// plane ahead of use), then writes them to LDS.
-template <class T>
-struct TileRec {
-    T v[2][5];
-    uint8_t f[2];
-};
-
-template <class T>
-__device__ __forceinline__ void colour_tile_fetch(TileRec<T>& r, int z, int x0, int y0,
-                                                  const T* __restrict__ phi_prev, const T* __restrict__ G,
-                                                  const uint8_t* __restrict__ flags, int nx, int ny, int nz,
-                                                  int64_t S) {
-    const int Z = wrapc(z, nz);
-#pragma unroll
-    for (int e = 0; e < 2; e++) {
-        const int k = threadIdx.x + e * CTX * CTY;
-        if (k < CRX * CRY) {
-            const int lx = k % CRX, ly = k / CRX;
-            const int X = wrapc(x0 + lx - 1, nx), Y = wrapc(y0 + ly - 1, ny);
-            const uint32_t id = (uint32_t)X + (uint32_t)nx * ((uint32_t)Y + (uint32_t)ny * (uint32_t)Z);
-            r.v[e][0] = ld(phi_prev, id);
-            r.v[e][1] = ld(G, id);
-            r.v[e][2] = ld(G + S, id);
-            r.v[e][3] = ld(G + 2 * S, id);
-            r.v[e][4] = ld(G + 3 * S, id);
-            r.f[e] = ld(flags, id);
-        }
-    }
-}
-
-// Fetch and store in one pass (one entry live at a time).
+// The record and flags of plane z for the tile and its ring, fetched and
+// stored to LDS in one pass (one entry live at a time).
 template <class T>
 __device__ __forceinline__ void colour_tile_load(ColourSmem<T>& sm, int z, int x0, int y0,
                                                  const T* __restrict__ phi_prev, const T* __restrict__ G,
@@ -682,21 +637,6 @@ __device__ __forceinline__ void colour_tile_load(ColourSmem<T>& sm, int z, int x
     }
 }
 
-template <class T>
-__device__ __forceinline__ void colour_tile_store(ColourSmem<T>& sm, const TileRec<T>& r, int z) {
-    const int sl = slotc(z);
-#pragma unroll
-    for (int e = 0; e < 2; e++) {
-        const int k = threadIdx.x + e * CTX * CTY;
-        if (k < CRX * CRY) {
-            const int lx = k % CRX, ly = k / CRX;
-#pragma unroll
-            for (int q = 0; q < 5; q++) sm.rec[sl][q][ly][lx] = r.v[e][q];
-            sm.fl[sl][ly][lx] = r.f[e];
-        }
-    }
-}
-
 template <class T, class SN>
 __global__ __launch_bounds__(CTX * CTY) void k_colour_tile(const SN* __restrict__ N, const T* __restrict__ phi_prev,
                                                            const T* __restrict__ G, const uint8_t* __restrict__ flags,
@@ -713,35 +653,15 @@ __global__ __launch_bounds__(CTX * CTY) void k_colour_tile(const SN* __restrict_
     const int64_t S = P.S;
     const uint32_t xy = (uint32_t)(x0 + tx) + (uint32_t)P.nx * (uint32_t)(y0 + ty);
     const uint32_t plane = (uint32_t)P.nx * (uint32_t)P.ny;
-    constexpr int AHEAD = (CSL - 1) / 2;   // planes loaded ahead of the one computed
-    for (int zz = z0 - 1; zz < z0 + AHEAD; zz++)
+    for (int zz = z0 - 1; zz < z0 + 1; zz++)
         colour_tile_load<T>(sm, zz, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
     SN raw[19];
-#if LBM_COLOUR_PIPE
-    TileRec<T> rec;
-    SN nxt[19];
-    colour_tile_fetch<T>(rec, z0 + 1, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
-#pragma unroll
-    for (int i = 0; i < 19; i++) raw[i] = ld_nt(N + (int64_t)i * S, xy + plane * (uint32_t)z0);
-#endif
     for (int z = z0; z < z1; z++) {
-#if LBM_COLOUR_PIPE
-        // the record of plane z + 1 (fetched during the previous plane) into
-        // LDS, then the loads of the next plane before this plane's arithmetic
-        colour_tile_store<T>(sm, rec, z + 1);
-        __syncthreads();
-        if (z + 1 < z1) {
-#pragma unroll
-            for (int i = 0; i < 19; i++) nxt[i] = ld_nt(N + (int64_t)i * S, xy + plane * (uint32_t)(z + 1));
-        }
-        colour_tile_fetch<T>(rec, z + 2, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
-#else
-        // N of plane z, the record of plane z + AHEAD into LDS
+        // N of plane z, the record of plane z + 1 into LDS
 #pragma unroll
         for (int i = 0; i < 19; i++) raw[i] = ld_nt(N + (int64_t)i * S, xy + plane * (uint32_t)z);
-        colour_tile_load<T>(sm, z + AHEAD, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
+        colour_tile_load<T>(sm, z + 1, x0, y0, phi_prev, G, flags, P.nx, P.ny, P.nz, S);
         __syncthreads();
-#endif
         const int s0 = slotc(z), sx = tx + 1, sy = ty + 1;
         const uint8_t f = sm.fl[s0][sy][sx];
         if (!(f & FLAG_SOLID)) {
@@ -770,175 +690,9 @@ __global__ __launch_bounds__(CTX * CTY) void k_colour_tile(const SN* __restrict_
             });
             st(phi, xy + plane * (uint32_t)z, acc);
         }
-        // With three slots the next load overwrites a plane this one read;
-        // with five, the next iteration's barrier already orders them.
-        if (CSL == 3 || LBM_COLOUR_PIPE) __syncthreads();
-#if LBM_COLOUR_PIPE
-#pragma unroll
-        for (int i = 0; i < 19; i++) raw[i] = nxt[i];
-#endif
-    }
-}
-
-// The tiled colour kernel with G re-formed in LDS (the collide then writes
-// only p of the record): G(y) = (2/W) max(phi(1-phi), 0) grad phi/|grad phi|
-// from the same phi_prev field and the same stencil the collision used, so
-// it equals the stored G bit for bit.  LDS per workgroup: phi_prev of four
-// planes on the tile and a two-node ring, and G, p, flags of three planes on
-// the tile and a one-node ring.  It saves 24 B per node of HBM traffic
-// (FP32) but forms G for the ring too and needs a third barrier per plane:
-// measured slower at 256^3 (FP32 17.5k against 17.7k MLUPS, FP16 23.0k
-// against 25.6k), so it is built only with LBM_G_RECOMPUTE=1.
-#ifndef LBM_G_RECOMPUTE
-#define LBM_G_RECOMPUTE 0
-#endif
-constexpr int CQX = CTX + 4, CQY = CTY + 4;       // tile + two rings
-
-template <class T>
-struct ColourSmemG {
-    T ph[4][CQY][CQX];         // phi_prev, planes by slot4(z)
-    T g[3][3][CRY][CRX];       // G, planes by slot3(z)
-    T p[3][CRY][CRX];
-    uint8_t fl[3][CRY][CRX];
-};
-
-__device__ __forceinline__ int slot4(int z) { return (z % 4 + 4) % 4; }
-
-template <class T>
-__device__ __forceinline__ void colour_g_load_phi(ColourSmemG<T>& sm, int z, int x0, int y0,
-                                                  const T* __restrict__ phi_prev, int nx, int ny, int nz) {
-    const int sl = slot4(z);
-    const int Z = wrapc(z, nz);
-    for (int k = threadIdx.x; k < CQX * CQY; k += CTX * CTY) {
-        const int lx = k % CQX, ly = k / CQX;
-        const int X = wrapc(x0 + lx - 2, nx), Y = wrapc(y0 + ly - 2, ny);
-        sm.ph[sl][ly][lx] = ld(phi_prev, (uint32_t)X + (uint32_t)nx * ((uint32_t)Y + (uint32_t)ny * (uint32_t)Z));
-    }
-}
-
-template <class T>
-__device__ __forceinline__ void colour_g_load_pf(ColourSmemG<T>& sm, int z, int x0, int y0,
-                                                 const T* __restrict__ prec, const uint8_t* __restrict__ flags,
-                                                 int nx, int ny, int nz) {
-    const int sl = slot3(z);
-    const int Z = wrapc(z, nz);
-    for (int k = threadIdx.x; k < CRX * CRY; k += CTX * CTY) {
-        const int lx = k % CRX, ly = k / CRX;
-        const int X = wrapc(x0 + lx - 1, nx), Y = wrapc(y0 + ly - 1, ny);
-        const uint32_t id = (uint32_t)X + (uint32_t)nx * ((uint32_t)Y + (uint32_t)ny * (uint32_t)Z);
-        sm.p[sl][ly][lx] = ld(prec, id);
-        sm.fl[sl][ly][lx] = ld(flags, id);
-    }
-}
-
-// G of plane z on the tile and its ring from phi_prev of planes z-1..z+1.
-template <class T>
-__device__ __forceinline__ void colour_g_form(ColourSmemG<T>& sm, int z, const KParams<T, 19>& P) {
-    using L = LatD3Q19;
-    const int sg = slot3(z);
-    for (int k = threadIdx.x; k < CRX * CRY; k += CTX * CTY) {
-        const int lx = k % CRX, ly = k / CRX;
-        T ph[19];
-        static_for<0, 19>([&](auto ic) {
-            constexpr int i = decltype(ic)::value;
-            ph[i] = sm.ph[slot4(z + L::c[i][2])][ly + 1 + L::c[i][1]][lx + 1 + L::c[i][0]];
-        });
-        T gx, gy, gz, G[3];
-        grad_stencil<L, T>(ph, gx, gy, gz);
-        recolour_vector<T>(ph[0], gx, gy, gz, P.inv_W, P.n_thresh2, G);
-        sm.g[sg][0][ly][lx] = G[0];
-        sm.g[sg][1][ly][lx] = G[1];
-        sm.g[sg][2][ly][lx] = G[2];
-    }
-}
-
-template <class T, class SN>
-__global__ __launch_bounds__(CTX * CTY) void k_colour_tile_g(const SN* __restrict__ N, const T* __restrict__ phi_prev,
-                                                             const T* __restrict__ prec,
-                                                             const uint8_t* __restrict__ flags, T* __restrict__ phi,
-                                                             KParams<T, 19> P, TileSched ts, int zc) {
-    using L = LatD3Q19;
-    __shared__ ColourSmemG<T> sm;
-    int bx, by, bz;
-    tile_index(ts, bx, by, bz);
-    const int x0 = bx * CTX, y0 = by * CTY;
-    const int z0 = bz * zc;
-    const int z1 = min(z0 + zc, P.nz);
-    const int tx = threadIdx.x % CTX, ty = threadIdx.x / CTX;
-    const int64_t S = P.S;
-    const uint32_t xy = (uint32_t)(x0 + tx) + (uint32_t)P.nx * (uint32_t)(y0 + ty);
-    const uint32_t plane = (uint32_t)P.nx * (uint32_t)P.ny;
-    for (int z = z0 - 2; z <= z0 + 1; z++) colour_g_load_phi<T>(sm, z, x0, y0, phi_prev, P.nx, P.ny, P.nz);
-    colour_g_load_pf<T>(sm, z0 - 1, x0, y0, prec, flags, P.nx, P.ny, P.nz);
-    colour_g_load_pf<T>(sm, z0, x0, y0, prec, flags, P.nx, P.ny, P.nz);
-    __syncthreads();
-    colour_g_form<T>(sm, z0 - 1, P);
-    colour_g_form<T>(sm, z0, P);
-    __syncthreads();   // phi_prev of plane z0 - 2 is overwritten next
-    for (int z = z0; z < z1; z++) {
-        // N of plane z; phi_prev of plane z + 2, p and flags of plane z + 1
-        SN raw[19];
-#pragma unroll
-        for (int i = 0; i < 19; i++) raw[i] = ld_nt(N + (int64_t)i * S, xy + plane * (uint32_t)z);
-        colour_g_load_phi<T>(sm, z + 2, x0, y0, phi_prev, P.nx, P.ny, P.nz);
-        colour_g_load_pf<T>(sm, z + 1, x0, y0, prec, flags, P.nx, P.ny, P.nz);
-        __syncthreads();
-        colour_g_form<T>(sm, z + 1, P);
-        __syncthreads();
-        const int s0 = slot3(z), sx = tx + 1, sy = ty + 1;
-        const uint8_t f = sm.fl[s0][sy][sx];
-        if (!(f & FLAG_SOLID)) {
-            const bool near = (f & FLAG_NEAR_SOLID) != 0;
-            T acc = 0;
-            static_for<0, L::Q>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-                const T n = NStore<T, SN>::dec(raw[i], P.n_s);
-                if constexpr (i == 0) {
-                    acc += sm.ph[slot4(z)][sy + 1][sx + 1] * (P.chi[0] + n);
-                } else {
-                    int zs = z - cz, qx = sx - cx, qy = sy - cy;
-                    T sgn = T(1);
-                    if (near && (sm.fl[slot3(zs)][qy][qx] & FLAG_SOLID)) {
-                        zs = z;
-                        qx = sx;
-                        qy = sy;
-                        sgn = T(-1);
-                    }
-                    const int sl = slot3(zs);
-                    const T gx = cx != 0 ? sm.g[sl][0][qy][qx] : T(0);
-                    const T gy = cy != 0 ? sm.g[sl][1][qy][qx] : T(0);
-                    const T gz = cz != 0 ? sm.g[sl][2][qy][qx] : T(0);
-                    acc += compact_term<L, T, i>(n, sm.ph[slot4(zs)][qy + 1][qx + 1], gx, gy, gz, sm.p[sl][qy][qx],
-                                                 sgn, P);
-                }
-            });
-            st(phi, xy + plane * (uint32_t)z, acc);
-        }
+        // the next load overwrites the plane below, which this one read
         __syncthreads();
     }
-}
-
-// G planes of the record re-formed from phi_prev at every fluid node (for
-// the row, batched and read-out kernels after steps that left them
-// unwritten).
-template <class L, class T>
-__global__ __launch_bounds__(256) void k_g_record(const T* __restrict__ phi_prev, const uint8_t* __restrict__ flags,
-                                                  T* __restrict__ G, KParams<T, L::Q> P) {
-    RowIdx r;
-    if (!row_index(P.nx, P.ny, r)) return;
-    const uint32_t x = (uint32_t)r.x;
-    if (ld(flags, x) & FLAG_SOLID) return;
-    uint32_t nb[L::Q];
-    neighbours<L>(r.ix, r.iy, r.iz, P.nx, P.ny, P.nz, nb);
-    T ph[L::Q];
-#pragma unroll
-    for (int i = 0; i < L::Q; i++) ph[i] = ld(phi_prev, nb[i]);
-    T gx, gy, gz, Gv[3];
-    grad_stencil<L, T>(ph, gx, gy, gz);
-    recolour_vector<T>(ph[0], gx, gy, gz, P.inv_W, P.n_thresh2, Gv);
-#pragma unroll
-    for (int a = 0; a < L::D; a++) st(G + (int64_t)a * P.S, x, Gv[a]);
 }
 
 // One direction plane of B from the compact record into FP64 (read-out).
@@ -1004,7 +758,7 @@ __global__ __launch_bounds__(256) void k_ghost(const int32_t* __restrict__ g_nod
 // Fused stencil + forces + collision + recolouring + push streaming with
 // halfway bounce-back, one node.  Writes the streamed N* and the node's
 // compact liquid record (G, p).
-template <class L, class T, class SN, bool WG = true>
+template <class L, class T, class SN, bool NT = true>
 __device__ __forceinline__ void collide_core(const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
                                              T* __restrict__ Gdst, const T* __restrict__ phi,
                                              const uint8_t* __restrict__ flags, const KParams<T, L::Q>& P,
@@ -1014,7 +768,7 @@ __device__ __forceinline__ void collide_core(const SN* __restrict__ Nsrc, SN* __
     const int64_t S = P.S;
     T N[Q], ph[Q];
 #pragma unroll
-    for (int i = 0; i < Q; i++) N[i] = NS::dec(ld_nt(Nsrc + (int64_t)i * S, x), P.n_s);
+    for (int i = 0; i < Q; i++) N[i] = NS::dec(NT ? ld_nt(Nsrc + (int64_t)i * S, x) : ld(Nsrc + (int64_t)i * S, x), P.n_s);
 #pragma unroll
     for (int i = 0; i < Q; i++) ph[i] = ld(phi, nb[i]);
     Macro<T> m;
@@ -1041,15 +795,13 @@ __device__ __forceinline__ void collide_core(const SN* __restrict__ Nsrc, SN* __
 #pragma unroll
         for (int i = 0; i < Q; i++) st(Ndst + (int64_t)i * S, nb[i], e[i]);
     }
-    if constexpr (WG) {
 #pragma unroll
-        for (int a = 0; a < L::D; a++) st(Gdst + (int64_t)a * S, x, G[a]);
-    }
+    for (int a = 0; a < L::D; a++) st(Gdst + (int64_t)a * S, x, G[a]);
     st(Gdst + (int64_t)GRec<L>::P * S, x, m.p);
 }
 
 // The same for the node at (ix, iy, iz) of the box layout.
-template <class L, class T, class SN, bool WG = true>
+template <class L, class T, class SN, bool NT = true>
 __device__ __forceinline__ void collide_node(const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
                                              T* __restrict__ Gdst, const T* __restrict__ phi,
                                              const uint8_t* __restrict__ flags, const KParams<T, L::Q>& P, int ix,
@@ -1059,53 +811,409 @@ __device__ __forceinline__ void collide_node(const SN* __restrict__ Nsrc, SN* __
     if (f & FLAG_SOLID) return;
     uint32_t nb[L::Q];
     neighbours<L>(ix, iy, iz, P.nx, P.ny, P.nz, nb);
-    collide_core<L, T, SN, WG>(Nsrc, Ndst, Gdst, phi, flags, P, x, f, nb);
+    collide_core<L, T, SN, NT>(Nsrc, Ndst, Gdst, phi, flags, P, x, f, nb);
 }
 
-// One thread per node of an x-row.  WG = false leaves the G planes of the
-// record unwritten (the tiled colour kernel re-forms G from phi).
-template <class L, class T, class SN, bool WG = true>
+// One thread per node of an x-row.
+template <class L, class T, class SN>
 __global__ __launch_bounds__(LBM_COLLIDE_BX) void k_collide_stream(const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
                                                                    T* __restrict__ Gdst, const T* __restrict__ phi,
                                                                    const uint8_t* __restrict__ flags,
                                                                    KParams<T, L::Q> P, RowSched rs) {
     RowIdx r;
     if (!row_index_sched(rs, P.nx, r)) return;
-    collide_node<L, T, SN, WG>(Nsrc, Ndst, Gdst, phi, flags, P, r.ix, r.iy, r.iz);
+    collide_node<L, T, SN>(Nsrc, Ndst, Gdst, phi, flags, P, r.ix, r.iy, r.iz);
 }
 
-// Fluid-list forms of the two row kernels: one thread per fluid node of an
-// ascending id list, so no lane idles on a solid node (packings); the
-// per-node functions are the same.
-__device__ __forceinline__ void list_coords(int32_t id, int nx, int ny, int& ix, int& iy, int& iz) {
-    const uint32_t u = (uint32_t)id, a = u / (uint32_t)nx;
-    ix = (int)(u - a * (uint32_t)nx);
-    iy = (int)(a % (uint32_t)ny);
-    iz = (int)(a / (uint32_t)ny);
+// ------------------------------------------------------------------ collide-colour step
+// D3Q19 boxes tiled by KTX x KTY columns run each step as one collide launch
+// that also forms the next step's colour field, plus a small fix-up launch.
+// Streaming moves the recoloured B*_i(x) to x + c_i exactly as it moves
+// N*_i(x), so phi(y) = sum_i B_i(y) of the next step is the sum of the
+// recoloured populations arriving at y (Eq. A12, A13, A17).  A workgroup
+// owns a KTX x KTY column and marches up a chunk of planes.  Each node
+// collides, pushes N* to its neighbours in HBM, forms its B*_i from the
+// stored N*_i (the value the two-pass colour kernel reads back) and its own
+// phi, G and p, and hands each B*_i to the node it streams to through LDS.
+// That node adds what it receives in direction order: the c_z = 0 group when
+// its own plane is done, the c_z = +1 group (from the plane below, kept from
+// the previous iteration) right after, and the c_z = -1 group when the plane
+// above is done, so a node whose sources all lie in its tile gets exactly
+// the two-pass sum.  A value whose source lies outside the target's tile or
+// z-chunk goes to the target tile's inbox in HBM instead; k_colour_fixup then
+// adds those, in direction order, to the in-tile partial sum.  Bounce-back
+// links deliver B*_i(x) to x itself in direction opp(i).  No compact record
+// is written: the liquid state after such a step is phi itself.
+constexpr int KTX = 64, KTY = 8;   // collide-colour tile
+constexpr int KNT = KTX * KTY;     // threads per workgroup
+constexpr int KRING = 2 * KTX + 2 * (KTY - 2);   // nodes on a tile's lateral edge
+
+// Index of direction I among the five D3Q19 directions with c[I][A] == S.
+template <int I, int A, int S>
+__device__ __host__ constexpr int cross_k() {
+    int k = 0;
+    for (int j = 0; j < I; j++)
+        if (LatD3Q19::c[j][A] == S) k++;
+    return k;
 }
 
-template <class L, class T, class SN>
-__global__ __launch_bounds__(256) void k_colour_list(const int32_t* __restrict__ list, int64_t n_list,
-                                                     const SN* __restrict__ N, const T* __restrict__ phi_prev,
-                                                     const T* __restrict__ G, const uint8_t* __restrict__ flags,
-                                                     T* __restrict__ phi, KParams<T, L::Q> P) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_list) return;
-    int ix, iy, iz;
-    list_coords(list[k], P.nx, P.ny, ix, iy, iz);
-    colour_compact_node<L, T, SN>(N, phi_prev, G, flags, phi, P, ix, iy, iz);
+// Inbox of one tile-chunk (values of T): for targets on its x faces the
+// directions arriving across them ([2 sides][5][zc][KTY]), then the y faces
+// ([2][5][zc][KTX]), then the chunk's bottom and top planes ([2][5][KTY][KTX]).
+// A value crossing several faces is filed under x, then y, then z.
+__host__ __device__ constexpr int64_t cross_tile_vals(int zc) {
+    return 10 * (int64_t)zc * (KTX + KTY) + 10 * (int64_t)KNT;
 }
 
-template <class L, class T, class SN>
-__global__ __launch_bounds__(256) void k_collide_list(const int32_t* __restrict__ list, int64_t n_list,
-                                                      const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
-                                                      T* __restrict__ Gdst, const T* __restrict__ phi,
-                                                      const uint8_t* __restrict__ flags, KParams<T, L::Q> P) {
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n_list) return;
-    int ix, iy, iz;
-    list_coords(list[k], P.nx, P.ny, ix, iy, iz);
-    collide_node<L, T, SN>(Nsrc, Ndst, Gdst, phi, flags, P, ix, iy, iz);
+// Slot of direction I arriving at local (lx, ly, lz) of a tile-chunk with
+// zlen planes, or -1 when its source (lx, ly, lz) - c_I lies in the same
+// tile-chunk.
+template <int I>
+__device__ __forceinline__ int cross_slot(int lx, int ly, int lz, int zc, int zlen) {
+    constexpr int cx = LatD3Q19::c[I][0], cy = LatD3Q19::c[I][1], cz = LatD3Q19::c[I][2];
+    const int sx = lx - cx, sy = ly - cy, sz = lz - cz;
+    if (cx != 0 && (sx < 0 || sx >= KTX)) {
+        constexpr int side = cx > 0 ? 0 : 1, k = cross_k<I, 0, cx>();
+        return ((side * 5 + k) * zc + lz) * KTY + ly;
+    }
+    if (cy != 0 && (sy < 0 || sy >= KTY)) {
+        constexpr int side = cy > 0 ? 0 : 1, k = cross_k<I, 1, cy>();
+        return 10 * zc * KTY + ((side * 5 + k) * zc + lz) * KTX + lx;
+    }
+    if (cz != 0 && (sz < 0 || sz >= zlen)) {
+        constexpr int side = cz > 0 ? 0 : 1, k = cross_k<I, 2, cz>();
+        return 10 * zc * (KTX + KTY) + ((side * 5 + k) * KTY + ly) * KTX + lx;
+    }
+    return -1;
+}
+
+struct CrossGeom {
+    int xt, yt;    // tiles in x and y
+    int zc;        // planes per z-chunk (the last chunk may be shorter)
+    int nzc;       // z-chunks
+};
+
+// Lateral face-crossing values of one plane, staged in LDS by source
+// position and copied to the inbox after the barrier (coalesced, by all
+// threads, instead of by the few edge lanes of each wave): the x ring holds
+// the five directions leaving through each x face ([2][5][KTY], by source
+// y), the y ring the five leaving through each y face without leaving
+// through an x face ([2][5][KTX], by source x).
+constexpr int XRING = 2 * 5 * KTY, YRING = 2 * 5 * KTX;
+
+// Target tile-chunk (absolute inbox offset of its block) and local z of a
+// value leaving plane lz of chunk bz along c_z = cz (the same chunk unless
+// it crosses the chunk's bottom or top plane).
+__device__ __forceinline__ void cross_target_z(const CrossGeom& cg, int nz, int bz, int zlen, int lz, int cz, int& tbz,
+                                               int& tz, int& tzlen) {
+    tbz = bz;
+    tz = lz + cz;
+    tzlen = zlen;
+    if (tz >= zlen) {
+        tbz = bz == cg.nzc - 1 ? 0 : bz + 1;
+        tz = 0;
+        tzlen = min(cg.zc, nz - tbz * cg.zc);
+    } else if (tz < 0) {
+        tbz = bz == 0 ? cg.nzc - 1 : bz - 1;
+        tzlen = min(cg.zc, nz - tbz * cg.zc);
+        tz = tzlen - 1;
+    }
+}
+
+template <class T, class SN>
+__global__ __launch_bounds__(KNT, sizeof(T) == 8 ? 2 : 4) void k_collide_colour(const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
+                                                        const T* __restrict__ phi, T* __restrict__ phi_out,
+                                                        T* __restrict__ cross, const uint8_t* __restrict__ flags,
+                                                        KParams<T, 19> P, TileSched ts, CrossGeom cg) {
+    using L = LatD3Q19;
+    using NS = NStore<T, SN>;
+    constexpr int Q = 19;
+    __shared__ T xch[2][Q - 1][KTY][KTX];   // [iteration parity][direction - 1][target y][target x]
+    __shared__ T ring[2][XRING + YRING];     // [iteration parity] the plane's lateral face-crossing values
+    int bx, by, bz;
+    tile_index(ts, bx, by, bz);
+    const int x0 = bx * KTX, y0 = by * KTY, z0 = bz * cg.zc;
+    const int z1 = min(z0 + cg.zc, P.nz), zlen = z1 - z0;
+    const int tx = threadIdx.x % KTX, ty = threadIdx.x / KTX;
+    const int ix = x0 + tx, iy = y0 + ty;
+    const int64_t S = P.S;
+    const int64_t tvals = cross_tile_vals(cg.zc);
+    const uint32_t plane = (uint32_t)P.nx * (uint32_t)P.ny;
+    const uint32_t xy = (uint32_t)ix + (uint32_t)P.nx * (uint32_t)iy;
+    // per thread, fixed for the whole march: bit i of lat_out is set when
+    // x + c_i leaves the tile laterally, bit i of lat_in when x - c_i lies in it
+    uint32_t lat_out = 0, lat_in = 0;
+    static_for<1, Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int cx = L::c[i][0], cy = L::c[i][1];
+        if (tx + cx < 0 || tx + cx >= KTX || ty + cy < 0 || ty + cy >= KTY) lat_out |= 1u << i;
+        if (tx - cx >= 0 && tx - cx < KTX && ty - cy >= 0 && ty - cy < KTY) lat_in |= 1u << i;
+    });
+    // neighbour offsets in x and y (periodic wrap at the box faces)
+    const int oxp = ix == P.nx - 1 ? 1 - P.nx : 1, oxm = ix == 0 ? P.nx - 1 : -1;
+    const int oyp = iy == P.ny - 1 ? (1 - P.ny) * P.nx : P.nx, oym = iy == 0 ? (P.ny - 1) * P.nx : -P.nx;
+    T acc_prev = T(0);      // partial colour sum of (ix, iy, z - 1): c_z = 0 and +1 groups
+    uint32_t m_prev = 0;    // bit i: direction i arrives at (ix, iy, z - 1) by bounce-back; bit 31: fluid
+    uint8_t f_next = ld(flags, xy + plane * (uint32_t)z0);   // flags one plane ahead
+    for (int z = z0; z < z1; z++) {
+        const int buf = (z - z0) & 1;
+        const int lz = z - z0;
+        const uint32_t x = xy + plane * (uint32_t)z;
+        const uint8_t f = f_next;
+        if (z + 1 < z1) f_next = ld(flags, x + plane);
+        const bool fluid = !(f & FLAG_SOLID);
+        uint32_t m = fluid ? 0x80000000u : 0u;
+        T b0 = T(0);
+        T bbu[5];           // c_z = +1 directions arriving at this node by bounce-back
+#pragma unroll
+        for (int k = 0; k < 5; k++) bbu[k] = T(0);
+        if (fluid) {
+            const int ozp = z == P.nz - 1 ? (1 - P.nz) * (int)plane : (int)plane;
+            const int ozm = z == 0 ? (P.nz - 1) * (int)plane : -(int)plane;
+            auto nbr = [&](auto ic) -> uint32_t {
+                constexpr int i = decltype(ic)::value;
+                constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+                int o = 0;
+                if constexpr (cx > 0) o += oxp;
+                if constexpr (cx < 0) o += oxm;
+                if constexpr (cy > 0) o += oyp;
+                if constexpr (cy < 0) o += oym;
+                if constexpr (cz > 0) o += ozp;
+                if constexpr (cz < 0) o += ozm;
+                return x + (uint32_t)o;
+            };
+            T N[Q], ph[Q];
+#pragma unroll
+            for (int i = 0; i < Q; i++) N[i] = NS::dec(ld_nt(Nsrc + (int64_t)i * S, x), P.n_s);
+            ph[0] = ld(phi, x);
+            uint32_t bbm = 0;   // bit i: x + c_i is solid (bounce-back link)
+            const bool near = (f & FLAG_NEAR_SOLID) != 0;
+            static_for<1, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                const uint32_t y = nbr(ic);
+                ph[i] = ld(phi, y);
+                if (near && (ld(flags, y) & FLAG_SOLID)) bbm |= 1u << i;
+            });
+            Macro<T> mc;
+            T Pi[6];
+            macro_stage<L, T>(N, ph, P, mc, Pi);
+            T Ns[Q], G[3];
+            collide_stage<L, T>(mc, Pi, P, Ns, G);
+            SN e[Q];
+            T closure = P.n_close;
+#pragma unroll
+            for (int i = 1; i < Q; i++) {
+                e[i] = NS::enc(Ns[i], P.n_inv_s);
+                closure -= NS::off(e[i]);
+            }
+            e[0] = NS::enc_off(closure);
+            st(Ndst, x, e[0]);   // the rest population stays at x
+            b0 = mc.phi * (P.chi[0] + NS::dec(e[0], P.n_s));
+            static_for<1, Q>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                constexpr int j = L::opp[i];
+                constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+                const T b = compact_term<L, T, i>(NS::dec(e[i], P.n_s), mc.phi, G[0], G[1], G[2], mc.p, T(1), P);
+                if ((bbm >> i) & 1u) {
+                    // bounce-back: N*_i and B*_i return to x in direction opp(i)
+                    st(Ndst + (int64_t)j * S, x, e[i]);
+                    m |= 1u << j;
+                    if constexpr (L::c[j][2] == 0) xch[buf][j - 1][ty][tx] = b;   // its source is solid: slot free
+                    else if constexpr (L::c[j][2] > 0) bbu[j - 9] = b;
+                    else xch[buf ^ 1][j - 1][ty][tx] = b;   // read back with the plane above (own slot)
+                } else {
+                    st(Ndst + (int64_t)i * S, nbr(ic), e[i]);
+                    if ((lat_out >> i) & 1u) {
+                        // leaves the tile through a lateral face: staged in the ring
+                        if (tx + cx < 0 || tx + cx >= KTX) {
+                            if constexpr (cx != 0) ring[buf][((cx > 0 ? 5 : 0) + cross_k<i, 0, cx>()) * KTY + ty] = b;
+                        } else {
+                            if constexpr (cy != 0)
+                                ring[buf][XRING + ((cy > 0 ? 5 : 0) + cross_k<i, 1, cy>()) * KTX + tx] = b;
+                        }
+                    } else if ((cz > 0 && lz + 1 == zlen) || (cz < 0 && lz == 0)) {
+                        // leaves the chunk through its top or bottom plane (the
+                        // whole workgroup takes this branch together)
+                        int tbz, tz, tzlen;
+                        cross_target_z(cg, P.nz, bz, zlen, lz, cz, tbz, tz, tzlen);
+                        const int64_t t = ((int64_t)tbz * cg.yt + by) * cg.xt + bx;
+                        cross[t * tvals + cross_slot<i>(tx + cx, ty + cy, tz, cg.zc, tzlen)] = b;
+                    } else {
+                        xch[buf][i - 1][ty + cy][tx + cx] = b;
+                    }
+                }
+            });
+        }
+        // c_z = +1 values for this plane, handed over in the previous
+        // iteration's buffer (read before this barrier: the next iteration
+        // overwrites that buffer only after it)
+        T upv[5];
+#pragma unroll
+        for (int k = 0; k < 5; k++) upv[k] = lz > 0 ? xch[buf ^ 1][9 + k - 1][ty][tx] : T(0);
+        __syncthreads();
+        // the ring's values to the inbox of the tile they enter (entries of
+        // solid or bounce-back sources hold stale values; the fix-up reads
+        // only entries of fluid sources)
+        for (int k = threadIdx.x; k < XRING + YRING; k += KNT) {
+            const T v = ring[buf][k];
+            if (k < XRING) {
+                const int pr = k / KTY, sy = k % KTY;     // pair (side, direction), source y
+                static_for<0, 10>([&](auto pc) {
+                    constexpr int pp = decltype(pc)::value;
+                    constexpr int side = pp / 5, kk = pp % 5;
+                    constexpr int i = L::dir_with<0, side ? 1 : -1>(kk);
+                    constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+                    if (pr == pp) {
+                        const int sx = cx > 0 ? KTX - 1 : 0;
+                        int ttx = sx + cx, tty = sy + cy, tbx, tby = by;
+                        tbx = cx > 0 ? (bx == cg.xt - 1 ? 0 : bx + 1) : (bx == 0 ? cg.xt - 1 : bx - 1);
+                        ttx -= cx > 0 ? KTX : -KTX;
+                        if (tty < 0) { tty += KTY; tby = by == 0 ? cg.yt - 1 : by - 1; }
+                        if (tty >= KTY) { tty -= KTY; tby = by == cg.yt - 1 ? 0 : by + 1; }
+                        int tbz, tz, tzlen;
+                        cross_target_z(cg, P.nz, bz, zlen, lz, cz, tbz, tz, tzlen);
+                        const int64_t t = ((int64_t)tbz * cg.yt + tby) * cg.xt + tbx;
+                        cross[t * tvals + cross_slot<i>(ttx, tty, tz, cg.zc, tzlen)] = v;
+                    }
+                });
+            } else {
+                const int q = k - XRING;
+                const int pr = q / KTX, sx = q % KTX;     // pair (side, direction), source x
+                static_for<0, 10>([&](auto pc) {
+                    constexpr int pp = decltype(pc)::value;
+                    constexpr int side = pp / 5, kk = pp % 5;
+                    constexpr int i = L::dir_with<1, side ? 1 : -1>(kk);
+                    constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+                    if (pr == pp && sx + cx >= 0 && sx + cx < KTX) {   // x-face crossings are in the x ring
+                        const int sy = cy > 0 ? KTY - 1 : 0;
+                        const int tty = sy + cy - (cy > 0 ? KTY : -KTY);
+                        const int tby = cy > 0 ? (by == cg.yt - 1 ? 0 : by + 1) : (by == 0 ? cg.yt - 1 : by - 1);
+                        int tbz, tz, tzlen;
+                        cross_target_z(cg, P.nz, bz, zlen, lz, cz, tbz, tz, tzlen);
+                        const int64_t t = ((int64_t)tbz * cg.yt + tby) * cg.xt + bx;
+                        cross[t * tvals + cross_slot<i>(sx + cx, tty, tz, cg.zc, tzlen)] = v;
+                    }
+                });
+            }
+        }
+        T acc = T(0);
+        if (fluid) {
+            const uint32_t take = m | lat_in;   // bounce-back, or a source in the tile
+            acc = b0;
+            static_for<1, 9>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                if ((take >> i) & 1u) acc += xch[buf][i - 1][ty][tx];
+            });
+            static_for<9, 14>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                if ((m >> i) & 1u) acc += bbu[i - 9];
+                else if (((lat_in >> i) & 1u) && lz > 0) acc += upv[i - 9];
+            });
+        }
+        if (m_prev & 0x80000000u) {
+            // the plane below is complete with the c_z = -1 values from this plane
+            const uint32_t take = m_prev | lat_in;
+            T s = acc_prev;
+            static_for<14, 19>([&](auto ic) {
+                constexpr int i = decltype(ic)::value;
+                if ((take >> i) & 1u) s += xch[buf][i - 1][ty][tx];
+            });
+            st(phi_out, x - plane, s);
+        }
+        acc_prev = acc;
+        m_prev = m;
+    }
+    if (m_prev & 0x80000000u) {
+        // top plane of the chunk: its c_z = -1 sources lie in the next chunk
+        // (bounce-back values were left in the other buffer)
+        const int buf = zlen & 1;
+        T s = acc_prev;
+        static_for<14, 19>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            if ((m_prev >> i) & 1u) s += xch[buf][i - 1][ty][tx];
+        });
+        st(phi_out, xy + plane * (uint32_t)(z1 - 1), s);
+    }
+}
+
+// Adds the inbox values (sources outside the target's tile-chunk) to the
+// in-tile partial sums, in direction order.  The nodes that have such
+// sources are, in each tile-chunk, every node of its first and last plane
+// and the KRING nodes on the tile's lateral edge in the planes between;
+// they are numbered densely, FIXUP_BLOCKS(zc) workgroups per tile-chunk.
+__host__ __device__ constexpr int fixup_nodes(int zlen) {
+    return zlen >= 2 ? 2 * KNT + (zlen - 2) * KRING : KNT;
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_colour_fixup(T* __restrict__ phi_out, const T* __restrict__ cross,
+                                                      const uint8_t* __restrict__ flags, int nx, int ny, int nz,
+                                                      CrossGeom cg, int blocks_per_chunk) {
+    using L = LatD3Q19;
+    const int tc = (int)(blockIdx.x / (unsigned)blocks_per_chunk);   // tile-chunk
+    const int k = (int)(blockIdx.x % (unsigned)blocks_per_chunk) * 256 + (int)threadIdx.x;
+    const int bx = tc % cg.xt, by = (tc / cg.xt) % cg.yt, bz = tc / (cg.xt * cg.yt);
+    const int zlen = min(cg.zc, nz - bz * cg.zc);
+    if (k >= fixup_nodes(zlen)) return;
+    int lx, ly, lz;
+    if (k < KNT) {
+        lz = 0;
+        lx = k % KTX;
+        ly = k / KTX;
+    } else if (k < 2 * KNT) {
+        lz = zlen - 1;
+        lx = (k - KNT) % KTX;
+        ly = (k - KNT) / KTX;
+    } else {
+        const int r = k - 2 * KNT;
+        lz = 1 + r / KRING;
+        const int q = r % KRING;
+        if (q < 2 * KTX) {
+            lx = q % KTX;
+            ly = q < KTX ? 0 : KTY - 1;
+        } else {
+            lx = q - 2 * KTX < KTY - 2 ? 0 : KTX - 1;
+            ly = 1 + (q - 2 * KTX) % (KTY - 2);
+        }
+    }
+    const int X = bx * KTX + lx, Y = by * KTY + ly, Z = bz * cg.zc + lz;
+    const uint32_t x = (uint32_t)X + (uint32_t)nx * ((uint32_t)Y + (uint32_t)ny * (uint32_t)Z);
+    const T* box = cross + (int64_t)tc * cross_tile_vals(cg.zc);
+    // every load is issued before any of them is used: the node's flags and
+    // partial sum and the inbox slots of its crossing directions
+    const uint8_t fx = ld(flags, x);
+    const T part = ld(phi_out, x);
+    T v[18];
+    static_for<1, 19>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        const int slot = cross_slot<i>(lx, ly, lz, cg.zc, zlen);
+        v[i - 1] = slot >= 0 ? box[slot] : T(0);
+    });
+    if (fx & FLAG_SOLID) return;
+    const bool near = (fx & FLAG_NEAR_SOLID) != 0;
+    T add = T(0);
+    bool any = false;
+    static_for<1, 19>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
+        if (cross_slot<i>(lx, ly, lz, cg.zc, zlen) >= 0) {
+            // a solid source is a bounce-back link, already in the partial
+            // sum; only a node next to a solid has one
+            bool take = true;
+            if (near) {
+                const int sx = X - cx < 0 ? nx - 1 : (X - cx >= nx ? 0 : X - cx);
+                const int sy = Y - cy < 0 ? ny - 1 : (Y - cy >= ny ? 0 : Y - cy);
+                const int sz = Z - cz < 0 ? nz - 1 : (Z - cz >= nz ? 0 : Z - cz);
+                take = !(ld(flags, (uint32_t)sx + (uint32_t)nx * ((uint32_t)sy + (uint32_t)ny * (uint32_t)sz)) &
+                         FLAG_SOLID);
+            }
+            if (take) {
+                add += v[i - 1];
+                any = true;
+            }
+        }
+    });
+    if (any) st(phi_out, x, part + add);
 }
 
 // Fluid-only ("sparse") layout for packings: node slots are the fluid nodes
@@ -1115,23 +1223,6 @@ __global__ __launch_bounds__(256) void k_collide_list(const int32_t* __restrict_
 // where the neighbour is solid).  The per-node functions are the box
 // layout's, so a step computes the same values bit for bit; only the
 // launches cover the fluid slots instead of the box.
-// Block order of the sparse launches.  The hardware deals consecutive
-// blocks round-robin to the eight XCDs; with LBM_SPARSE_XCD the blocks are
-// renumbered so that each XCD walks one contiguous eighth of the slots (its
-// L2 then still holds the neighbour planes a gather needs).
-#ifndef LBM_SPARSE_XCD
-#define LBM_SPARSE_XCD 0
-#endif
-__device__ __forceinline__ int64_t sparse_block() {
-#if LBM_SPARSE_XCD
-    const uint32_t nb = gridDim.x, b = blockIdx.x;
-    const uint32_t q = nb / 8, r = nb % 8, x = b % 8;
-    return (int64_t)(x * q + (x < r ? x : r) + b / 8);
-#else
-    return blockIdx.x;
-#endif
-}
-
 template <class L>
 __device__ __forceinline__ void sparse_neighbours(const uint32_t* __restrict__ nbt, int64_t nf, uint32_t k,
                                                   uint32_t (&nb)[L::Q]) {
@@ -1145,7 +1236,7 @@ __global__ __launch_bounds__(256) void k_colour_sparse(const uint32_t* __restric
                                                        const SN* __restrict__ N, const T* __restrict__ phi_prev,
                                                        const T* __restrict__ G, const uint8_t* __restrict__ flags,
                                                        T* __restrict__ phi, KParams<T, L::Q> P) {
-    const int64_t k = sparse_block() * blockDim.x + threadIdx.x;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nf) return;
     uint32_t nb[L::Q];
     sparse_neighbours<L>(nbt, nf, (uint32_t)k, nb);
@@ -1157,11 +1248,11 @@ __global__ __launch_bounds__(256) void k_collide_sparse(const uint32_t* __restri
                                                         const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
                                                         T* __restrict__ Gdst, const T* __restrict__ phi,
                                                         const uint8_t* __restrict__ flags, KParams<T, L::Q> P) {
-    const int64_t k = sparse_block() * blockDim.x + threadIdx.x;
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nf) return;
     uint32_t nb[L::Q];
     sparse_neighbours<L>(nbt, nf, (uint32_t)k, nb);
-    collide_core<L, T, SN, true>(Nsrc, Ndst, Gdst, phi, flags, P, (uint32_t)k, ld(flags, (uint32_t)k), nb);
+    collide_core<L, T, SN>(Nsrc, Ndst, Gdst, phi, flags, P, (uint32_t)k, ld(flags, (uint32_t)k), nb);
 }
 
 // u and p of every slot (solid slots get 0), sparse layout.
@@ -1316,7 +1407,7 @@ __global__ __launch_bounds__(256) void k_reduce1(const SN* __restrict__ N, const
         v[6] += 0.5 * rho * u2;
         if (!isfinite(ph) || !isfinite(u2)) bad++;
         for (int i = 0; i < L::Q; i++)
-            if (!isfinite((double)(float)N[(int64_t)i * S + x])) bad++;
+            if (!isfinite((double)NStore<T, SN>::off(N[(int64_t)i * S + x]))) bad++;
         for (int i = 0; i < nB; i++)
             if (!isfinite((double)Bstate[(int64_t)i * S + x])) bad++;
     }
@@ -1427,6 +1518,15 @@ __global__ __launch_bounds__(256) void k_plane_in(const double* __restrict__ src
     dst[x] = (T)src[x];
 }
 
+// Fluid entries of one colour buffer from an FP64 plane.
+template <class T>
+__global__ __launch_bounds__(256) void k_fluid_in(const double* __restrict__ src, const uint8_t* __restrict__ flags,
+                                                  T* __restrict__ phi, int64_t n) {
+    const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (x >= n) return;
+    if (!(flags[x] & FLAG_SOLID)) phi[x] = (T)src[x];
+}
+
 // Solid entries of both colour buffers from an FP64 plane.
 template <class T>
 __global__ __launch_bounds__(256) void k_solid_in(const double* __restrict__ src, const uint8_t* __restrict__ flags,
@@ -1436,239 +1536,6 @@ __global__ __launch_bounds__(256) void k_solid_in(const double* __restrict__ src
     if (flags[x] & FLAG_SOLID) {
         phiA[x] = (T)src[x];
         phiB[x] = (T)src[x];
-    }
-}
-
-// ------------------------------------------------------------------ fused D3Q19 step
-// One launch per step (after the ghost pre-pass) for D3Q19 boxes whose x and
-// y extents are multiples of the tile: every workgroup owns a 32 x 8 column
-// of nodes and marches up a chunk of z-planes.  For each plane it forms
-// phi^{n+1} = sum_i B_i on the tile and a one-node ring from the compact
-// record (staged in LDS for the tile and two rings, three planes deep), then
-// collides the plane below from registers: each node's N is read from HBM
-// once per step (the ring's N comes from L2), phi^{n+1} never leaves the
-// workgroup except as next step's record.  Arithmetic per node is the same
-// as the colour and fused kernels of the two-launch step.
-constexpr int FTX = 32, FTY = 8;                 // tile
-constexpr int FRX = FTX + 2, FRY = FTY + 2;      // tile + 1 ring (phi window)
-constexpr int FSX = FTX + 4, FSY = FTY + 4;      // tile + 2 rings (record window)
-constexpr int FKS = 5;                           // phi_prev, Gx, Gy, Gz, p
-
-// Ghost pre-pass of the fused step: like k_ghost, but the fluid corners'
-// phi^{n+1} are formed here from the compact record (the colour field of
-// this step is not stored anywhere else).
-template <class L, class T, class SN>
-__global__ __launch_bounds__(256) void k_ghost_direct(const int32_t* __restrict__ g_node,
-                                                      const int32_t* __restrict__ g_corner,
-                                                      const T* __restrict__ g_w, const uint8_t* __restrict__ g_mask,
-                                                      int ng, const SN* __restrict__ N, const T* __restrict__ phiA,
-                                                      const T* __restrict__ G, const uint8_t* __restrict__ flags,
-                                                      T* __restrict__ phiB, T E, T eps, int rule,
-                                                      KParams<T, L::Q> P) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ng) return;
-    const uint32_t mask = g_mask[g];
-    T f = 0;
-#pragma unroll 1
-    for (int k = 0; k < L::NC; k++) {
-        const int32_t c = g_corner[(int64_t)k * ng + g];
-        T v;
-        if ((mask >> k) & 1u) {
-            v = phiA[c];
-        } else {
-            const int ix = c % P.nx, iy = (c / P.nx) % P.ny, iz = c / (P.nx * P.ny);
-            uint32_t nb[L::Q];
-            neighbours<L>(ix, iy, iz, P.nx, P.ny, P.nz, nb);
-            const bool near = (flags[c] & FLAG_NEAR_SOLID) != 0;
-            T acc = 0;
-            static_for<0, L::Q>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                acc += compact_B<L, T, SN, i>(N, phiA, G, flags, P, (uint32_t)c, nb, near);
-            });
-            v = acc;
-        }
-        f += g_w[(int64_t)k * ng + g] * v;
-    }
-    T out;
-    if (rule == 0) {
-        out = f / (f + (T(1) - f) * E);
-    } else {
-        const T a = T(1) + T(0.5) * eps;
-        out = T(4) * f / (a + sqrt(a * a - T(2) * eps * f)) - f;
-    }
-    phiB[g_node[g]] = out;
-}
-
-template <class T, class SN>
-struct FusedSmem {
-    T rec[3][FKS][FSY][FSX];   // record window: planes by slot3(z)
-    uint8_t fl[3][FSY][FSX];   // flags of the same nodes
-    T phi[3][FRY][FRX];        // phi^{n+1} window: planes by slot3(z)
-};
-
-// Stage the record and flags of plane z (tile + two rings) into LDS.
-template <class T, class SN>
-__device__ __forceinline__ void fused_load_plane(FusedSmem<T, SN>& sm, int z, int x0, int y0,
-                                                 const T* __restrict__ phiA, const T* __restrict__ G,
-                                                 const uint8_t* __restrict__ flags, const KParams<T, 19>& P) {
-    const int s = slot3(z);
-    const int Z = wrapc(z, P.nz);
-    const int64_t S = P.S;
-    for (int k = threadIdx.x; k < FSX * FSY; k += FTX * FTY) {
-        const int lx = k % FSX, ly = k / FSX;
-        const int X = wrapc(x0 + lx - 2, P.nx), Y = wrapc(y0 + ly - 2, P.ny);
-        const int64_t id = (int64_t)X + (int64_t)P.nx * ((int64_t)Y + (int64_t)P.ny * Z);
-        sm.rec[s][0][ly][lx] = phiA[id];
-        sm.rec[s][1][ly][lx] = G[id];
-        sm.rec[s][2][ly][lx] = G[S + id];
-        sm.rec[s][3][ly][lx] = G[2 * S + id];
-        sm.rec[s][4][ly][lx] = G[3 * S + id];
-        sm.fl[s][ly][lx] = flags[id];
-    }
-}
-
-// phi^{n+1} of one node of plane z at tile-local (lx, ly) in [-1, FTX] x
-// [-1, FTY]; N of the node is returned (decoded) for reuse.
-template <class T, class SN>
-__device__ __forceinline__ T fused_phi_node(const FusedSmem<T, SN>& sm, int z, int lx, int ly, int64_t id,
-                                            const SN* __restrict__ N, const T* __restrict__ phiB,
-                                            const KParams<T, 19>& P, T (&n)[19]) {
-    using L = LatD3Q19;
-    const int sx = lx + 2, sy = ly + 2;
-    const uint8_t f = sm.fl[slot3(z)][sy][sx];
-    if (f & FLAG_SOLID) return phiB[id];
-    const bool near = (f & FLAG_NEAR_SOLID) != 0;
-    T acc = 0;
-    static_for<0, L::Q>([&](auto ic) {
-        constexpr int i = decltype(ic)::value;
-        constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-        n[i] = NStore<T, SN>::dec(N[(int64_t)i * P.S + id], P.n_s);
-        if constexpr (i == 0) {
-            acc += sm.rec[slot3(z)][0][sy][sx] * (P.chi[0] + n[0]);
-        } else {
-            int s = slot3(z - cz), qx = sx - cx, qy = sy - cy;
-            T sgn = T(1);
-            if (near && (sm.fl[s][qy][qx] & FLAG_SOLID)) {
-                s = slot3(z);
-                qx = sx;
-                qy = sy;
-                sgn = T(-1);
-            }
-            acc += compact_term<L, T, i>(n[i], sm.rec[s][0][qy][qx], sm.rec[s][1][qy][qx], sm.rec[s][2][qy][qx],
-                                         sm.rec[s][3][qy][qx], sm.rec[s][4][qy][qx], sgn, P);
-        }
-    });
-    return acc;
-}
-
-// Form phi^{n+1} of plane z on the tile and its ring into the phi window;
-// the thread's own tile node keeps its N in `mine`.  Tile values inside the
-// chunk are also written to phiB (next step's record).
-template <class T, class SN>
-__device__ __forceinline__ void fused_form_plane(FusedSmem<T, SN>& sm, int z, int z0, int z1, int x0, int y0,
-                                                 const SN* __restrict__ N, T* __restrict__ phiB,
-                                                 const KParams<T, 19>& P, T (&mine)[19]) {
-    const int tx = threadIdx.x % FTX, ty = threadIdx.x / FTX;
-    const int Z = wrapc(z, P.nz);
-    const int sp = slot3(z);
-    {
-        const int X = x0 + tx, Y = y0 + ty;
-        const int64_t id = (int64_t)X + (int64_t)P.nx * ((int64_t)Y + (int64_t)P.ny * Z);
-        const T v = fused_phi_node<T, SN>(sm, z, tx, ty, id, N, phiB, P, mine);
-        sm.phi[sp][ty + 1][tx + 1] = v;
-        if (z >= z0 && z < z1 && !(sm.fl[sp][ty + 2][tx + 2] & FLAG_SOLID)) phiB[id] = v;
-    }
-    // ring: 2 (FTX + 2) + 2 FTY nodes, one per thread
-    constexpr int NR = 2 * (FTX + 2) + 2 * FTY;
-    const int r = threadIdx.x;
-    if (r < NR) {
-        int lx, ly;
-        if (r < FTX + 2) { lx = r - 1; ly = -1; }
-        else if (r < 2 * (FTX + 2)) { lx = r - (FTX + 2) - 1; ly = FTY; }
-        else if (r < 2 * (FTX + 2) + FTY) { lx = -1; ly = r - 2 * (FTX + 2); }
-        else { lx = FTX; ly = r - 2 * (FTX + 2) - FTY; }
-        const int X = wrapc(x0 + lx, P.nx), Y = wrapc(y0 + ly, P.ny);
-        const int64_t id = (int64_t)X + (int64_t)P.nx * ((int64_t)Y + (int64_t)P.ny * Z);
-        T scratch[19];
-        sm.phi[sp][ly + 1][lx + 1] = fused_phi_node<T, SN>(sm, z, lx, ly, id, N, phiB, P, scratch);
-    }
-}
-
-template <class T, class SN>
-__global__ __launch_bounds__(FTX * FTY) void k_step_fused(const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
-                                                          const T* __restrict__ phiA, T* __restrict__ phiB,
-                                                          const T* __restrict__ Gsrc, T* __restrict__ Gdst,
-                                                          const uint8_t* __restrict__ flags, KParams<T, 19> P,
-                                                          int zc) {
-    using L = LatD3Q19;
-    constexpr int Q = 19;
-    __shared__ FusedSmem<T, SN> sm;
-    const int x0 = blockIdx.x * FTX, y0 = blockIdx.y * FTY;
-    const int z0 = blockIdx.z * zc;
-    const int z1 = min(z0 + zc, P.nz);
-    const int tx = threadIdx.x % FTX, ty = threadIdx.x / FTX;
-    T ncur[Q], nnext[Q];
-    // prologue: phi of planes z0 - 1 and z0
-    fused_load_plane<T, SN>(sm, z0 - 2, x0, y0, phiA, Gsrc, flags, P);
-    fused_load_plane<T, SN>(sm, z0 - 1, x0, y0, phiA, Gsrc, flags, P);
-    fused_load_plane<T, SN>(sm, z0, x0, y0, phiA, Gsrc, flags, P);
-    __syncthreads();
-    fused_form_plane<T, SN>(sm, z0 - 1, z0, z1, x0, y0, Nsrc, phiB, P, nnext);
-    __syncthreads();
-    fused_load_plane<T, SN>(sm, z0 + 1, x0, y0, phiA, Gsrc, flags, P);
-    __syncthreads();
-    fused_form_plane<T, SN>(sm, z0, z0, z1, x0, y0, Nsrc, phiB, P, ncur);
-    for (int z = z0; z < z1; z++) {
-        __syncthreads();
-        fused_load_plane<T, SN>(sm, z + 2, x0, y0, phiA, Gsrc, flags, P);
-        __syncthreads();
-        fused_form_plane<T, SN>(sm, z + 1, z0, z1, x0, y0, Nsrc, phiB, P, nnext);
-        __syncthreads();
-        // collide plane z at the thread's node
-        const int sz = slot3(z);
-        if (!(sm.fl[sz][ty + 2][tx + 2] & FLAG_SOLID)) {
-            const int ix = x0 + tx, iy = y0 + ty, iz = z;
-            const int64_t x = (int64_t)ix + (int64_t)P.nx * ((int64_t)iy + (int64_t)P.ny * iz);
-            const uint8_t f = sm.fl[sz][ty + 2][tx + 2];
-            T ph[Q];
-            static_for<0, Q>([&](auto ic) {
-                constexpr int i = decltype(ic)::value;
-                constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-                ph[i] = sm.phi[slot3(z + cz)][ty + 1 + cy][tx + 1 + cx];
-            });
-            Macro<T> m;
-            T Pi[6];
-            macro_stage<L, T>(ncur, ph, P, m, Pi);
-            T Ns[Q], Gv[3];
-            collide_stage<L, T>(m, Pi, P, Ns, Gv);
-            using NS = NStore<T, SN>;
-            SN e[Q];
-            T closure = P.n_close;
-#pragma unroll
-            for (int i = 1; i < Q; i++) {
-                e[i] = NS::enc(Ns[i], P.n_inv_s);
-                closure -= NS::off(e[i]);
-            }
-            e[0] = NS::enc_off(closure);
-            int64_t nb[Q];
-            neighbours<L>(ix, iy, iz, P.nx, P.ny, P.nz, nb);
-            const int64_t S = P.S;
-            if (f & FLAG_NEAR_SOLID) {
-                static_for<0, Q>([&](auto ic) {
-                    constexpr int i = decltype(ic)::value;
-                    if (flags[nb[i]] & FLAG_SOLID) Ndst[(int64_t)L::opp[i] * S + x] = e[i];
-                    else Ndst[(int64_t)i * S + nb[i]] = e[i];
-                });
-            } else {
-#pragma unroll
-                for (int i = 0; i < Q; i++) Ndst[(int64_t)i * S + nb[i]] = e[i];
-            }
-#pragma unroll
-            for (int a = 0; a < 3; a++) Gdst[(int64_t)a * S + x] = Gv[a];
-            Gdst[3 * S + x] = m.p;
-        }
-#pragma unroll
-        for (int i = 0; i < Q; i++) ncur[i] = nnext[i];
     }
 }
 
@@ -1726,7 +1593,8 @@ __global__ __launch_bounds__(BATCH_BX) void kb_colour(const BJob<L, T, SN>* __re
     if (!batch_row(J, (int64_t)blockIdx.x - start[j], ix, iy, iz)) return;
     const int par = (int)((J.cur0 + k) & 1), pps = (int)((J.ps0 + k) & 1);
     T* work = J.phi[1 - pps];
-    if (k == 0 && J.planes0) {
+    if (k == 0 && J.planes0 == LIQ_PHI) return;   // phi of this sub-step already formed
+    if (k == 0 && J.planes0 == LIQ_PLANES) {
         const int64_t x = (int64_t)ix + (int64_t)J.P.nx * ((int64_t)iy + (int64_t)J.P.ny * iz);
         colour_planes_node<L, T>(J.B, work, J.flags, x, J.P.S);
     } else {
@@ -1754,8 +1622,10 @@ __global__ __launch_bounds__(BATCH_BX) void kb_collide(const BJob<L, T, SN>* __r
     int ix, iy, iz;
     if (!batch_row(J, (int64_t)blockIdx.x - start[j], ix, iy, iz)) return;
     const int par = (int)((J.cur0 + k) & 1), pps = (int)((J.ps0 + k) & 1);
-    collide_node<L, T, SN>(J.N[par], const_cast<SN*>(J.N[1 - par]), J.G[1 - par], J.phi[1 - pps], J.flags, J.P, ix,
-                           iy, iz);
+    // plain loads: the populations of most batched runs fit in the last-level
+    // cache and stay there between sub-steps (non-temporal loads give that up)
+    collide_node<L, T, SN, false>(J.N[par], const_cast<SN*>(J.N[1 - par]), J.G[1 - par], J.phi[1 - pps], J.flags,
+                                  J.P, ix, iy, iz);
 }
 
 // ------------------------------------------------------------------ launchers
@@ -1774,21 +1644,14 @@ static inline int row_block(int nx) {
     return b > LBM_COLLIDE_BX ? LBM_COLLIDE_BX : b;
 }
 
-// Row kernels run in plain row-major block order: a y-band order per XCD
-// (each XCD's L2 holding a stencil's y +- 1 rows) measured slower on gfx950
-// for both row kernels.  LBM_XCD_BANDS=1 builds it for comparison.
-#ifndef LBM_XCD_BANDS
-#define LBM_XCD_BANDS 0
-#endif
-#ifndef LBM_TILE_BANDS
-#define LBM_TILE_BANDS 1
-#endif
-
+// Row kernels run in plain row-major block order (a y-band order per XCD,
+// each XCD's L2 holding a stencil's y +- 1 rows, measured slower on gfx950
+// for both row kernels); colour tiles are dealt to the XCDs in y-bands.
 static inline RowSched row_sched(const StepParams& p, int bx) {
     RowSched s;
     s.xb = (p.nx + bx - 1) / bx;
     s.ny = p.ny;
-    s.band = (LBM_XCD_BANDS && p.ny % 8 == 0) ? p.ny / 8 : 0;
+    s.band = 0;
     return s;
 }
 
@@ -1796,13 +1659,9 @@ static inline dim3 row_grid1(const RowSched& s, const StepParams& p) {
     return dim3((unsigned)((int64_t)s.xb * p.ny * p.nz));
 }
 
-#ifndef LBM_COLOUR_TILE
-#define LBM_COLOUR_TILE 1
-#endif
-
 // The z-marching colour kernel takes D3Q19 boxes tiled exactly by CTX x CTY.
 static inline bool colour_tile_ok(const StepParams& p) {
-    return LBM_COLOUR_TILE && p.nz > 1 && p.nx % CTX == 0 && p.ny % CTY == 0;
+    return p.nz > 1 && p.nx % CTX == 0 && p.ny % CTY == 0;
 }
 
 // z-chunk: about LBM_CT_BLOCKS (2048) workgroups, at least 4 planes each.
@@ -1818,68 +1677,50 @@ static inline TileSched tile_sched(const StepParams& p) {
     TileSched s;
     s.xt = p.nx / CTX;
     s.yt = p.ny / CTY;
-    s.band = (LBM_TILE_BANDS && s.yt % 8 == 0) ? s.yt / 8 : 0;
+    s.band = s.yt % 8 == 0 ? s.yt / 8 : 0;
     return s;
 }
 
-// The fused one-launch step applies to D3Q19 boxes tiled exactly by 32 x 8
-// columns with at least 3 planes, once the liquid state is the compact record.
-static inline bool fused_ok(int lattice, const StepParams& p, int from_planes) {
-    // (opt-in: the workgroup-serial z-march is latency-bound on gfx950)
-    return lattice == 1 && !from_planes && p.nx % FTX == 0 && p.ny % FTY == 0 && p.nz >= 3;
-}
+// The collide-colour step takes D3Q19 boxes tiled exactly by KTX x KTY.
+static inline bool cc_ok(const StepParams& p) { return p.nx % KTX == 0 && p.ny % KTY == 0; }
 
-// z-chunk of the fused step: about 1024 workgroups, at least 4 planes each.
-static inline int fused_chunk(const StepParams& p) {
-    const int64_t cols = (int64_t)(p.nx / FTX) * (p.ny / FTY);
-    int64_t zc = (p.nz * cols + 1023) / 1024;
+// z-chunk of the collide-colour step: about LBM_CC_BLOCKS workgroups, at
+// least 4 planes each.
+#ifndef LBM_CC_BLOCKS
+#define LBM_CC_BLOCKS 2048
+#endif
+static inline CrossGeom cc_geom(const StepParams& p) {
+    CrossGeom g;
+    g.xt = p.nx / KTX;
+    g.yt = p.ny / KTY;
+    int64_t zc = ((int64_t)p.nz * g.xt * g.yt + LBM_CC_BLOCKS - 1) / LBM_CC_BLOCKS;
     if (zc < 4) zc = 4;
     if (zc > p.nz) zc = p.nz;
-    return (int)zc;
+    g.zc = (int)zc;
+    g.nzc = (p.nz + g.zc - 1) / g.zc;
+    return g;
+}
+
+bool step_fused(int lattice, const DevState& d, const StepParams& p) {
+    return lattice == 1 && d.fused && !d.sparse && cc_ok(p);
+}
+
+size_t cross_bytes(int lattice, uint32_t prec, const StepParams& p) {
+    if (lattice != 1 || !cc_ok(p)) return 0;
+    const CrossGeom g = cc_geom(p);
+    const int64_t chunks = (p.nz + g.zc - 1) / g.zc;
+    return (size_t)((int64_t)g.xt * g.yt * chunks * cross_tile_vals(g.zc)) * (prec == P_FP64 ? 8 : 4);
 }
 
 template <class L, class T, class SN>
-static hipError_t fused_phase_t(int phase, const DevState& d, const StepParams& p, int cur, int ps,
-                                hipStream_t st) {
-    if constexpr (L::D == 3) {
-        const KParams<T, L::Q> kp = make_kparams<T, L, SN>(p);
-        T* work = (T*)d.phi[1 - ps];
-        if (phase == 1 && d.n_ghost > 0) {
-            hipLaunchKernelGGL((k_ghost_direct<L, T, SN>), dim3(blocks_for(d.n_ghost, 256)), dim3(256), 0, st,
-                               d.g_node, d.g_corner, (const T*)d.g_w, d.g_mask, d.n_ghost, (const SN*)d.N[cur],
-                               (const T*)d.phi[ps], (const T*)d.G[cur], d.flags, work, (T)p.exp_eps, (T)p.eps,
-                               p.ghost_rule, kp);
-        } else if (phase == 2) {
-            const int zc = fused_chunk(p);
-            const dim3 grid((unsigned)(p.nx / FTX), (unsigned)(p.ny / FTY), (unsigned)((p.nz + zc - 1) / zc));
-            hipLaunchKernelGGL((k_step_fused<T, SN>), grid, dim3(FTX * FTY), 0, st, (const SN*)d.N[cur],
-                               (SN*)d.N[1 - cur], (const T*)d.phi[ps], work, (const T*)d.G[cur], (T*)d.G[1 - cur],
-                               d.flags, kp, zc);
-        }
-        return hipGetLastError();
-    } else {
-        (void)phase; (void)d; (void)p; (void)cur; (void)ps; (void)st;
-        return hipErrorNotSupported;
-    }
-}
-
-// Steps whose collide leaves the G planes of the record unwritten: the
-// colour kernel of the next step re-forms G in LDS (D3Q19 tiled boxes on the
-// dense-grid, two-launch path).
-template <class L>
-static inline bool g_mode(const DevState& d, const StepParams& p) {
-    return LBM_G_RECOMPUTE && L::D == 3 && !d.list && !d.sparse && !d.fused && colour_tile_ok(p);
-}
-
-template <class L, class T, class SN>
-static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int cur, int ps, int from_planes,
-                          hipStream_t st, bool allow_fused = true) {
-    if (allow_fused && d.fused && fused_ok(L::D == 3 ? 1 : 0, p, from_planes))
-        return fused_phase_t<L, T, SN>(phase, d, p, cur, ps, st);
+static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int cur, int ps, int liq,
+                          hipStream_t st) {
     T* work = (T*)d.phi[1 - ps];
     const int bx = row_block(p.nx);
+    const bool fused = step_fused(L::D == 3 ? 1 : 0, d, p);
     if (phase == 0) {
-        if (from_planes) {
+        if (liq == LIQ_PHI) return hipSuccess;   // formed by the last collide-colour step
+        if (liq == LIQ_PLANES) {
             hipLaunchKernelGGL((k_colour_planes<L, T>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st,
                                (const T*)d.B, work, d.flags, p.n, p.S);
         } else {
@@ -1891,27 +1732,13 @@ static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int
                                        (const T*)d.G[cur], d.flags, work, kp);
                 return hipGetLastError();
             }
-            if (d.list) {
-                if (d.n_fluid > 0)
-                    hipLaunchKernelGGL((k_colour_list<L, T, SN>), dim3(blocks_for(d.n_fluid, 256)), dim3(256), 0, st,
-                                       d.fluid, d.n_fluid, (const SN*)d.N[cur], (const T*)d.phi[ps],
-                                       (const T*)d.G[cur], d.flags, work, kp);
-                return hipGetLastError();
-            }
             if constexpr (L::D == 3) {
                 if (colour_tile_ok(p)) {
                     const int zc = colour_tile_chunk(p);
                     const TileSched ts = tile_sched(p);
                     const unsigned nb = (unsigned)(ts.xt * ts.yt * ((p.nz + zc - 1) / zc));
-                    if (g_mode<L>(d, p)) {
-                        hipLaunchKernelGGL((k_colour_tile_g<T, SN>), dim3(nb), dim3(CTX * CTY), 0, st,
-                                           (const SN*)d.N[cur], (const T*)d.phi[ps],
-                                           (const T*)d.G[cur] + (int64_t)GRec<L>::P * p.S, d.flags, work, kp, ts, zc);
-                    } else {
-                        hipLaunchKernelGGL((k_colour_tile<T, SN>), dim3(nb), dim3(CTX * CTY), 0, st,
-                                           (const SN*)d.N[cur], (const T*)d.phi[ps], (const T*)d.G[cur], d.flags,
-                                           work, kp, ts, zc);
-                    }
+                    hipLaunchKernelGGL((k_colour_tile<T, SN>), dim3(nb), dim3(CTX * CTY), 0, st, (const SN*)d.N[cur],
+                                       (const T*)d.phi[ps], (const T*)d.G[cur], d.flags, work, kp, ts, zc);
                     return hipGetLastError();
                 }
             }
@@ -1925,8 +1752,22 @@ static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int
                                d.g_corner, (const T*)d.g_w, d.g_mask, d.n_ghost, (const T*)d.phi[ps], work,
                                (T)p.exp_eps, (T)p.eps, p.ghost_rule);
         }
-    } else {
+    } else if (phase == 2) {
         const KParams<T, L::Q> kp = make_kparams<T, L, SN>(p);
+        if constexpr (L::D == 3) {
+            if (fused) {
+                // this step's phi (work) in, the next step's phi into phi[ps]
+                const CrossGeom g = cc_geom(p);
+                TileSched ts;
+                ts.xt = g.xt;
+                ts.yt = g.yt;
+                ts.band = g.yt % 8 == 0 ? g.yt / 8 : 0;
+                const unsigned nb = (unsigned)(g.xt * g.yt * ((p.nz + g.zc - 1) / g.zc));
+                hipLaunchKernelGGL((k_collide_colour<T, SN>), dim3(nb), dim3(KNT), 0, st, (const SN*)d.N[cur],
+                                   (SN*)d.N[1 - cur], (const T*)work, (T*)d.phi[ps], (T*)d.cross, d.flags, kp, ts, g);
+                return hipGetLastError();
+            }
+        }
         if (d.sparse) {
             if (d.n_fluid > 0)
                 hipLaunchKernelGGL((k_collide_sparse<L, T, SN>), dim3(blocks_for(d.n_fluid, 256)), dim3(256), 0, st,
@@ -1934,39 +1775,33 @@ static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int
                                    (const T*)work, d.flags, kp);
             return hipGetLastError();
         }
-        if (d.list) {
-            if (d.n_fluid > 0)
-                hipLaunchKernelGGL((k_collide_list<L, T, SN>), dim3(blocks_for(d.n_fluid, 256)), dim3(256), 0, st,
-                                   d.fluid, d.n_fluid, (const SN*)d.N[cur], (SN*)d.N[1 - cur], (T*)d.G[1 - cur],
-                                   (const T*)work, d.flags, kp);
-            return hipGetLastError();
-        }
         const RowSched rs = row_sched(p, bx);
-        if (g_mode<L>(d, p)) {
-            hipLaunchKernelGGL((k_collide_stream<L, T, SN, false>), row_grid1(rs, p), dim3(bx), 0, st,
-                               (const SN*)d.N[cur], (SN*)d.N[1 - cur], (T*)d.G[1 - cur], (const T*)work, d.flags, kp,
-                               rs);
-        } else {
-            hipLaunchKernelGGL((k_collide_stream<L, T, SN, true>), row_grid1(rs, p), dim3(bx), 0, st,
-                               (const SN*)d.N[cur], (SN*)d.N[1 - cur], (T*)d.G[1 - cur], (const T*)work, d.flags, kp,
-                               rs);
+        hipLaunchKernelGGL((k_collide_stream<L, T, SN>), row_grid1(rs, p), dim3(bx), 0, st, (const SN*)d.N[cur],
+                           (SN*)d.N[1 - cur], (T*)d.G[1 - cur], (const T*)work, d.flags, kp, rs);
+    } else {
+        if constexpr (L::D == 3) {
+            if (fused) {
+                const CrossGeom g = cc_geom(p);
+                const int bpc = (fixup_nodes(g.zc) + 255) / 256;
+                hipLaunchKernelGGL((k_colour_fixup<T>), dim3((unsigned)(g.xt * g.yt * g.nzc * bpc)), dim3(256), 0, st,
+                                   (T*)d.phi[ps], (const T*)d.cross, d.flags, p.nx, p.ny, p.nz, g, bpc);
+            }
         }
     }
     return hipGetLastError();
 }
 
 template <class L, class T, class SN>
-static hipError_t colour_t(const DevState& d, const StepParams& p, int cur, int ps, int from_planes,
-                           hipStream_t st) {
-    hipError_t e = phase_t<L, T, SN>(0, d, p, cur, ps, from_planes, st, false);
+static hipError_t colour_t(const DevState& d, const StepParams& p, int cur, int ps, int liq, hipStream_t st) {
+    hipError_t e = phase_t<L, T, SN>(0, d, p, cur, ps, liq, st);
     if (e != hipSuccess) return e;
-    return phase_t<L, T, SN>(1, d, p, cur, ps, from_planes, st, false);
+    return phase_t<L, T, SN>(1, d, p, cur, ps, liq, st);
 }
 
 template <class L, class T, class SN>
-static hipError_t step_t(const DevState& d, const StepParams& p, int cur, int ps, int from_planes, hipStream_t st) {
-    for (int ph = 0; ph < 3; ph++) {
-        hipError_t e = phase_t<L, T, SN>(ph, d, p, cur, ps, from_planes, st);
+static hipError_t step_t(const DevState& d, const StepParams& p, int cur, int ps, int liq, hipStream_t st) {
+    for (int ph = 0; ph < STEP_PHASES; ph++) {
+        hipError_t e = phase_t<L, T, SN>(ph, d, p, cur, ps, liq, st);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -1987,15 +1822,15 @@ static hipError_t macro_t(const DevState& d, const StepParams& p, int cur, int p
 }
 
 template <class L, class T, class SN>
-static hipError_t reduce_t(const DevState& d, const StepParams& p, int cur, int ps, int from_planes,
-                           hipStream_t st) {
-    const T* Bstate = from_planes ? (const T*)d.B : (const T*)d.G[cur];
-    const int nB = from_planes ? L::Q : GRec<L>::K;
+static hipError_t reduce_t(const DevState& d, const StepParams& p, int cur, int ps, int liq,
+                           const ReduceScratch& rs, hipStream_t st) {
+    const T* Bstate = liq == LIQ_PLANES ? (const T*)d.B : (const T*)d.G[cur];
+    const int nB = liq == LIQ_PLANES ? L::Q : (liq == LIQ_RECORD ? GRec<L>::K : 0);
     hipLaunchKernelGGL((k_reduce1<L, T, SN>), dim3(REDUCE_BLOCKS), dim3(256), 0, st, (const SN*)d.N[cur], Bstate, nB,
-                       (const T*)d.phi[1 - ps], d.flags, d.aux, p.n, p.S, p.rho_g, p.rho_l - p.rho_g, d.partial,
-                       d.nonfinite);
-    hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(256), 0, st, d.partial, d.nonfinite, REDUCE_BLOCKS, d.result,
-                       d.nonfinite + REDUCE_BLOCKS);
+                       (const T*)d.phi[1 - ps], d.flags, d.aux, p.n, p.S, p.rho_g, p.rho_l - p.rho_g, rs.partial,
+                       rs.nonfinite);
+    hipLaunchKernelGGL(k_reduce2, dim3(1), dim3(256), 0, st, rs.partial, rs.nonfinite, REDUCE_BLOCKS, rs.result,
+                       rs.nonfinite + REDUCE_BLOCKS);
     return hipGetLastError();
 }
 
@@ -2009,12 +1844,13 @@ static hipError_t init_t(const DevState& d, const StepParams& p, int cur, int ps
 }
 
 // which: 0 = N plane `dir` of buffer cur, 1 = B plane `dir` (planes buffer
-// when from_planes, else formed from the compact record), 2 = phi buffer `dir`,
+// in LIQ_PLANES, formed from the compact record in LIQ_RECORD), 2 = phi buffer `dir`,
 // 3 = N plane `dir` as the stored offset N_i - chi_i (exact in FP64).
 template <class L, class T, class SN>
-static hipError_t plane_out_t(const DevState& d, const StepParams& p, int which, int dir, int cur, int ps,
-                              int from_planes, hipStream_t st) {
-    if (which == 1 && !from_planes) {
+static hipError_t plane_out_t(const DevState& d, const StepParams& p, int which, int dir, int cur, int ps, int liq,
+                              hipStream_t st) {
+    if (which == 1 && liq == LIQ_PHI) return hipErrorInvalidValue;   // no B and no record to form it from
+    if (which == 1 && liq == LIQ_RECORD) {
         const KParams<T, L::Q> kp = make_kparams<T, L, SN>(p);
         if (d.sparse) {
             hipLaunchKernelGGL((k_compact_B_sparse<L, T, SN>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st, d.nbt,
@@ -2040,9 +1876,15 @@ static hipError_t plane_out_t(const DevState& d, const StepParams& p, int which,
 }
 
 // which: 0 = N plane `dir` of buffer cur, 1 = B plane `dir` (planes buffer),
-// 2 = solid entries of both phi buffers, 3 = N plane `dir` from offsets.
+// 2 = solid entries of both phi buffers, 3 = N plane `dir` from offsets,
+// 4 = fluid entries of phi buffer `dir`.
 template <class L, class T, class SN>
 static hipError_t plane_in_t(const DevState& d, const StepParams& p, int which, int dir, int cur, hipStream_t st) {
+    if (which == 4) {
+        hipLaunchKernelGGL((k_fluid_in<T>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st, d.aux, d.flags,
+                           (T*)d.phi[dir], p.n);
+        return hipGetLastError();
+    }
     if (which == 2) {
         hipLaunchKernelGGL((k_solid_in<T>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st, d.aux, d.flags,
                            (T*)d.phi[0], (T*)d.phi[1], p.n);
@@ -2076,54 +1918,39 @@ static hipError_t plane_in_t(const DevState& d, const StepParams& p, int which, 
         }                                                                             \
     } while (0)
 
-hipError_t launch_step(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
-                       int from_planes, hipStream_t st) {
-    LBM_DISPATCH(step_t, d, p, cur, ps, from_planes, st);
+hipError_t launch_step(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps, int liq,
+                       hipStream_t st) {
+    LBM_DISPATCH(step_t, d, p, cur, ps, liq, st);
 }
 hipError_t launch_phase(int lattice, uint32_t prec, int phase, const DevState& d, const StepParams& p, int cur,
-                        int ps, int from_planes, hipStream_t st) {
-    LBM_DISPATCH(phase_t, phase, d, p, cur, ps, from_planes, st);
+                        int ps, int liq, hipStream_t st) {
+    LBM_DISPATCH(phase_t, phase, d, p, cur, ps, liq, st);
 }
 hipError_t launch_colour(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
-                         int from_planes, hipStream_t st) {
-    LBM_DISPATCH(colour_t, d, p, cur, ps, from_planes, st);
+                         int liq, hipStream_t st) {
+    LBM_DISPATCH(colour_t, d, p, cur, ps, liq, st);
 }
 hipError_t launch_macro(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
                         hipStream_t st) {
     LBM_DISPATCH(macro_t, d, p, cur, ps, st);
 }
 hipError_t launch_reduce(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
-                         int from_planes, hipStream_t st) {
-    LBM_DISPATCH(reduce_t, d, p, cur, ps, from_planes, st);
+                         int liq, const ReduceScratch& rs, hipStream_t st) {
+    LBM_DISPATCH(reduce_t, d, p, cur, ps, liq, rs, st);
 }
 hipError_t launch_init(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
                        hipStream_t st) {
     LBM_DISPATCH(init_t, d, p, cur, ps, st);
 }
 hipError_t launch_plane_out(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int which, int dir,
-                            int cur, int ps, int from_planes, hipStream_t st) {
-    LBM_DISPATCH(plane_out_t, d, p, which, dir, cur, ps, from_planes, st);
+                            int cur, int ps, int liq, hipStream_t st) {
+    LBM_DISPATCH(plane_out_t, d, p, which, dir, cur, ps, liq, st);
 }
 hipError_t launch_plane_in(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int which, int dir,
                            int cur, hipStream_t st) {
     LBM_DISPATCH(plane_in_t, d, p, which, dir, cur, st);
 }
 
-template <class L, class T, class SN>
-static hipError_t g_record_t(const DevState& d, const StepParams& p, int cur, int ps, hipStream_t st) {
-    const KParams<T, L::Q> kp = make_kparams<T, L, SN>(p);
-    const int bx = row_block(p.nx);
-    hipLaunchKernelGGL((k_g_record<L, T>), row_grid(p, bx), dim3(bx), 0, st, (const T*)d.phi[ps], d.flags,
-                       (T*)d.G[cur], kp);
-    return hipGetLastError();
-}
-hipError_t launch_g_record(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
-                           hipStream_t st) {
-    LBM_DISPATCH(g_record_t, d, p, cur, ps, st);
-}
-bool steps_leave_g(int lattice, const DevState& d, const StepParams& p) {
-    return lattice == 1 ? g_mode<LatD3Q19>(d, p) : g_mode<LatD2Q9>(d, p);
-}
 // Per job: the descriptor and two block offsets; per group: alignment slack.
 static size_t batch_job_bytes() { return sizeof(BJob<LatD3Q19, double, double>) + 2 * sizeof(int64_t); }
 size_t batch_group_bytes(int njobs) { return (size_t)njobs * batch_job_bytes() + 1024; }

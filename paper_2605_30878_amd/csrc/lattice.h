@@ -35,6 +35,13 @@ struct LatD3Q19 {
                                      1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 18,
                                      1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 18,
                                      1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+    // The k-th direction (ascending) whose component A equals S.
+    template <int A, int S>
+    static constexpr int dir_with(int k) {
+        for (int i = 0; i < Q; i++)
+            if (c[i][A] == S && k-- == 0) return i;
+        return -1;
+    }
 };
 
 // Node classes stored in the flag array.

@@ -44,10 +44,9 @@ struct DevState {
     double* partial;    // [REDUCE_BLOCKS][8] reduction partials
     double* result;     // [8] reduced diagnostics
     int64_t* nonfinite; // [REDUCE_BLOCKS + 1]
-    int32_t fused;      // 1: D3Q19 steps use the fused one-launch form where the box allows it (opt-in)
-    int32_t* fluid;     // [n_fluid] fluid node ids, ascending
+    int32_t fused;      // 1: D3Q19 boxes tiled by the collide-colour tile step in the collide-colour form
+    void* cross;        // inbox of the collide-colour step (values crossing a tile-chunk face)
     int64_t n_fluid;
-    int32_t list;       // 1: colour and collide launch one thread per listed fluid node
     int32_t sparse;     // 1: fluid-only layout: planes hold one entry per slot (fluid nodes,
                         //    then ghost nodes, then one slot for every other solid node)
     uint32_t* nbt;      // [Q-1][n_fluid] sparse layout: slot of fluid node k + c_i
@@ -55,28 +54,51 @@ struct DevState {
 
 constexpr int REDUCE_BLOCKS = 1024;
 
+// Liquid state entering a step.
+enum Liquid : int {
+    LIQ_RECORD = 0,   // compact record (G, p) of the last collide in G[cur], its phi in phi[ps]
+    LIQ_PLANES = 1,   // B planes (initial state or a restore)
+    LIQ_PHI = 2       // the step's phi already formed in phi[1 - ps] at fluid nodes (collide-colour step)
+};
+
+// Launches of one step, in order: 0 colour field (none in LIQ_PHI), 1 ghost
+// update, 2 collide (two-pass collide-stream, or collide-colour), 3 colour
+// fix-up (collide-colour form only).
+constexpr int STEP_PHASES = 4;
+
 enum Precision : uint32_t { P_FP64 = 0, P_FP32 = 1, P_FP16_OFS = 2, P_BF16_OFS = 3 };
 
 // All launchers enqueue on `stream` and return hipGetLastError().
 // `cur` is the population / compact-record buffer holding the state, `ps`
-// the phi buffer holding the state's solid values (and the previous step's
-// phi at fluid nodes).  `from_planes` != 0: the liquid state is the B plane
-// buffer (initial state or restore) instead of the compact record.
-hipError_t launch_step(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
-                       int from_planes, hipStream_t stream);
-// One phase of a step: 0 = colour field, 1 = ghost update, 2 = fused
-// collide-stream (the three launches of launch_step, in that order).
+// the phi buffer holding the state's solid values (and, in LIQ_RECORD, the
+// previous step's phi at fluid nodes); `liq` is the liquid state (Liquid).
+hipError_t launch_step(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps, int liq,
+                       hipStream_t stream);
+// One phase of a step (STEP_PHASES, in order).
 hipError_t launch_phase(int lattice, uint32_t prec, int phase, const DevState& d, const StepParams& p, int cur,
-                        int ps, int from_planes, hipStream_t stream);
-// Colour field and ghost update into phi[1 - ps] (the phi the next step uses).
+                        int ps, int liq, hipStream_t stream);
+// True when a step of this run takes the collide-colour form (it then
+// leaves LIQ_PHI, otherwise LIQ_RECORD).
+bool step_fused(int lattice, const DevState& d, const StepParams& p);
+// Device bytes of the collide-colour inbox (0 when the box does not take it).
+size_t cross_bytes(int lattice, uint32_t prec, const StepParams& p);
+// Colour field (phase 0) and ghost update into phi[1 - ps] (the phi the next step uses).
 hipError_t launch_colour(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
-                         int from_planes, hipStream_t stream);
+                         int liq, hipStream_t stream);
 // u and p of every fluid node into aux (after launch_colour).
 hipError_t launch_macro(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
                         hipStream_t stream);
-// Diagnostics into d.result / d.nonfinite (after launch_macro).
+// Where the diagnostics reduce to: per-block partials [REDUCE_BLOCKS][8],
+// non-finite counters [REDUCE_BLOCKS + 1] (the last one the total) and the
+// result [8].  Every entry is overwritten by each reduction.
+struct ReduceScratch {
+    double* partial;
+    int64_t* nonfinite;
+    double* result;
+};
+// Diagnostics into rs (after launch_macro).
 hipError_t launch_reduce(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
-                         int from_planes, hipStream_t stream);
+                         int liq, const ReduceScratch& rs, hipStream_t stream);
 // Start of a run from the FP64 phi in aux[0]: N = chi, B = phi chi at fluid
 // nodes, phi of solid nodes (both buffers) = phi_solid.
 hipError_t launch_init(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
@@ -84,18 +106,13 @@ hipError_t launch_init(int lattice, uint32_t prec, const DevState& d, const Step
 // Solid nodes of both phi buffers = phi_solid.
 hipError_t launch_solid_phi(uint32_t prec, const DevState& d, const StepParams& p, hipStream_t stream);
 // One plane to FP64 aux[0].  which: 0 = N plane `dir`, 1 = B plane `dir`
-// (formed from the compact record unless from_planes), 2 = phi buffer `dir`.
+// (the plane buffer in LIQ_PLANES, formed from the compact record in
+// LIQ_RECORD, unavailable in LIQ_PHI), 2 = phi buffer `dir`, 3 = N offsets.
 hipError_t launch_plane_out(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int which,
-                            int dir, int cur, int ps, int from_planes, hipStream_t stream);
+                            int dir, int cur, int ps, int liq, hipStream_t stream);
 // One plane from FP64 aux[0].  which: 0 = N plane `dir`, 1 = B plane `dir`
-// of the plane buffer, 2 = solid entries of both phi buffers.
-// G planes of the compact record of buffer `cur` re-formed from phi[ps].
-hipError_t launch_g_record(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
-                           hipStream_t stream);
-// True when single-run steps leave the G planes of the record unwritten
-// (the tiled colour kernel re-forms them); row, batched and read-out
-// kernels then need launch_g_record first.
-bool steps_leave_g(int lattice, const DevState& d, const StepParams& p);
+// of the plane buffer, 2 = solid entries of both phi buffers, 3 = N offsets,
+// 4 = fluid entries of phi buffer `dir`.
 
 hipError_t launch_plane_in(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int which,
                            int dir, int cur, hipStream_t stream);
@@ -105,7 +122,7 @@ hipError_t launch_plane_in(int lattice, uint32_t prec, const DevState& d, const 
 struct BatchJobHost {
     DevState d;
     StepParams p;
-    int32_t cur0, ps0, planes0;
+    int32_t cur0, ps0, planes0;   // planes0: liquid state (Liquid) at the first sub-step
     int64_t steps;
 };
 

@@ -17,15 +17,15 @@ from . import workloads as W
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 OK, EINVAL, ESTATE, ENOMEM, EHIP, EUNSTABLE = 0, -1, -2, -3, -4, -5
 OPT_FUSED = 1
 OPT_FLUID_PROBE = 2
-OPT_FLUID_LIST = 4
 OPT_GRAPH = 8
 OPT_FILL_DEAD_ENDS = 16
 OPT_SPARSE = 32
-FIELD_PHI, FIELD_N, FIELD_B, FIELD_U, FIELD_P, FIELD_SOLID_PHI, FIELD_FLAGS, FIELD_N_OFFSET = range(8)
+(FIELD_PHI, FIELD_N, FIELD_B, FIELD_U, FIELD_P, FIELD_SOLID_PHI, FIELD_FLAGS, FIELD_N_OFFSET,
+ FIELD_PHI_STATE) = range(9)
 FLAG_SOLID, FLAG_NEAR_SOLID, FLAG_GHOST = 1, 2, 4
 
 EXPORTED = ["lbm_create", "lbm_set_geometry", "lbm_device_bytes", "lbm_bind", "lbm_set_wetting",
@@ -213,10 +213,11 @@ class Simulation:
         self._check(self.lib.lbm_step(self._h, int(nsteps)))
 
     def step_profiled(self, nsteps: int) -> Dict[str, float]:
-        """Step with per-launch HIP events; returns summed ms per phase."""
-        ms = np.zeros(4)
+        """Step with per-launch HIP events; returns summed ms per phase
+        (colour field, ghost update, collide, colour fix-up) and in all."""
+        ms = np.zeros(5)
         self._check(self.lib.lbm_step_profiled(self._h, int(nsteps), _dp(ms)))
-        return {"colour": ms[0], "ghost": ms[1], "collide": ms[2], "total": ms[3]}
+        return {"colour": ms[0], "ghost": ms[1], "collide": ms[2], "fixup": ms[3], "total": ms[4]}
 
     def read(self, field: int) -> np.ndarray:
         size = {FIELD_N: self.Q * self.n, FIELD_N_OFFSET: self.Q * self.n, FIELD_B: self.Q * self.n,

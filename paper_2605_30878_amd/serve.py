@@ -10,6 +10,11 @@ field, geometry, device state on its own stream) by worker threads while the
 resident batch computes, and joins the batch at the first tick after it is
 ready.  Latency is completion time minus arrival time on the host's
 monotonic clock.
+
+A run that goes non-finite is retired on its own with status "unstable"
+(checked when it finishes and every `check_ticks` ticks while it runs):
+the other runs of the batch, each in its own device buffer, go on and
+compute exactly what they compute alone.
 """
 from __future__ import annotations
 
@@ -44,6 +49,7 @@ class Result:
     steps: int
     obs: Dict[str, object]
     state: Optional[Dict[str, np.ndarray]] = None
+    status: str = "ok"            # "ok", or "unstable" (non-finite state; retired early)
 
     @property
     def latency(self) -> float:
@@ -103,7 +109,7 @@ def poisson_arrivals(reqs: Sequence[Request], rate: float, seed: int = 1) -> Lis
 class Server:
     def __init__(self, hbm_budget: float = 64e9, max_slots: int = 256, tick_steps: int = 200,
                  device: str = "cuda:0", keep_state: bool = False, progress_s: float = 0.0,
-                 prep_workers: int = 2):
+                 prep_workers: int = 2, check_ticks: int = 10):
         import torch
 
         self.torch = torch
@@ -114,6 +120,7 @@ class Server:
         self.keep_state = keep_state
         self.progress_s = float(progress_s)   # > 0: a progress line on stderr this often
         self.prep_workers = max(1, int(prep_workers))
+        self.check_ticks = int(check_ticks)   # > 0: look for non-finite runs this often (in ticks)
         self.stream = torch.cuda.current_stream(self.device)
         self.init_stream = torch.cuda.Stream(device=self.device)
         self.batch = lbm.Batch(max_jobs=max_slots, device=device, stream=self.stream)
@@ -136,6 +143,7 @@ class Server:
         t0 = time.monotonic()
         i = 0
         busy = False
+        ticks = 0
         last_report = 0.0
         pool = ThreadPoolExecutor(max_workers=self.prep_workers)
         try:
@@ -172,16 +180,23 @@ class Server:
                 if busy:
                     self.stream.synchronize()
                     busy = False
+                    ticks += 1
+                    check = self.check_ticks > 0 and ticks % self.check_ticks == 0
                     still = []
                     for rec in resident:
                         r, sim, remaining, adm, nb = rec
-                        if remaining == 0:
-                            obs = sim.observe()
+                        obs = None
+                        if remaining == 0 or check:
+                            # a non-finite run is reported, not raised: it
+                            # leaves alone and the batch goes on
+                            obs = sim.observe(allow_unstable=True)
+                        if remaining == 0 or (obs is not None and obs["nonfinite"] != 0):
+                            status = "ok" if obs["nonfinite"] == 0 else "unstable"
                             state = None
-                            if self.keep_state:
+                            if self.keep_state and status == "ok":
                                 state = {"N": sim.read(lbm.FIELD_N_OFFSET), "B": sim.read(lbm.FIELD_B)}
                             results.append(Result(r.rid, r.arrival, adm, time.monotonic() - t0, r.workload.nodes,
-                                                  r.steps, obs, state))
+                                                  int(obs["step"]), obs, state, status))
                             sim.close()
                             del sim
                             used -= nb
@@ -218,11 +233,16 @@ class Server:
 
 
 def summarize(results: Sequence[Result], wall: float) -> Dict[str, float]:
-    lat = np.array([r.latency for r in results])
+    """Latency percentiles and throughput over the runs that completed; the
+    lattice updates of unstable runs (up to their retirement) count in the
+    aggregate rate, the runs themselves are counted apart."""
+    done = [r for r in results if r.status == "ok"]
+    lat = np.array([r.latency for r in done]) if done else np.zeros(1)
     lups = sum(r.nodes * r.steps for r in results)
-    return {"jobs": len(results), "p50_latency_s": float(np.percentile(lat, 50)),
-            "p99_latency_s": float(np.percentile(lat, 99)), "mean_latency_s": float(lat.mean()),
-            "throughput_jobs_s": len(results) / wall, "aggregate_mlups": lups / wall / 1e6, "wall_s": wall}
+    return {"jobs": len(done), "unstable_jobs": len(results) - len(done),
+            "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
+            "mean_latency_s": float(lat.mean()), "throughput_jobs_s": len(done) / wall,
+            "aggregate_mlups": lups / wall / 1e6, "wall_s": wall}
 
 
 def serve_mix(count: int = 64, step_scale: float = 0.1, size_scale: float = 1.0, precision: int = W.FP32,
@@ -243,7 +263,7 @@ def serve_mix(count: int = 64, step_scale: float = 0.1, size_scale: float = 1.0,
     srv.close()
     return {"closed_loop": closed, "open_loop": opened, "arrival_rate_jobs_s": rate, "requests": count,
             "step_scale": step_scale, "precision": W.PRECISION_NAMES[precision],
-            "nonfinite_jobs": sum(1 for r in res if r.obs["nonfinite"] != 0)}
+            "nonfinite_jobs": sum(1 for r in res if r.status != "ok")}
 
 
 def main():

@@ -30,11 +30,16 @@ def rel_linf(a: np.ndarray, b: np.ndarray) -> float:
     return float(np.max(np.abs(a - b))) / den
 
 
-def fields_lib(sim, fluid_only_mask=None):
+def fields_lib(sim, with_b: bool = True):
+    """The library's state as FP64 arrays.  with_b=False for runs stepped in
+    the collide-colour form, which keep phi and no liquid populations."""
     from paper_2605_30878_amd import lbm
 
-    return {"N": sim.read(lbm.FIELD_N), "B": sim.read(lbm.FIELD_B), "phi": sim.read(lbm.FIELD_PHI),
-            "u": sim.read(lbm.FIELD_U), "p": sim.read(lbm.FIELD_P), "solid_phi": sim.read(lbm.FIELD_SOLID_PHI)}
+    out = {"N": sim.read(lbm.FIELD_N), "phi": sim.read(lbm.FIELD_PHI), "u": sim.read(lbm.FIELD_U),
+           "p": sim.read(lbm.FIELD_P), "solid_phi": sim.read(lbm.FIELD_SOLID_PHI)}
+    if with_b:
+        out["B"] = sim.read(lbm.FIELD_B)
+    return out
 
 
 def fields_orc(osim, perm):

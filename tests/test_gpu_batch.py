@@ -118,9 +118,10 @@ def test_small_served_mix_matches_single_runs():
 
 @pytest.mark.parametrize("prec", [W.FP32, W.FP16_OFS], ids=["f32", "fp16ofs"])
 def test_batch_after_tiled_single_steps(prec):
-    """A 64^3 run stepped alone (tiled colour kernel, G re-formed in LDS and
-    not stored), then in a batch (G rebuilt first), then alone again equals
-    the same run stepped alone throughout, bit for bit."""
+    """A 64^3 run stepped alone (tiled colour kernel), then in a batch (row
+    kernels over the job table), then alone again equals the same run
+    stepped alone throughout, bit for bit: the launch forms share their
+    per-node functions."""
     lbm = _lbm()
     wl = W.sphere_d3q19(64, theta=60.0, precision=prec)
     phi0 = W.initial_phi(wl)
@@ -142,6 +143,32 @@ def test_batch_after_tiled_single_steps(prec):
         s.close()
 
 
+@pytest.mark.parametrize("prec", [W.FP32, W.FP16_OFS], ids=["f32", "fp16ofs"])
+def test_batch_after_collide_colour_steps(prec):
+    """A run stepped in the collide-colour form (its phi already formed, no
+    compact record) joins a batch, whose first sub-step takes that phi, and
+    continues there; it agrees with the run stepped in the two-pass form
+    throughout to rounding (the colour sums differ in order at column
+    faces), and the batched part writes the record again (B readable)."""
+    lbm = _lbm()
+    wl = W.sphere_d3q19(64, theta=60.0, precision=prec)
+    phi0 = W.initial_phi(wl)
+    a = lbm.Simulation(wl, phi0, options=lbm.OPT_FUSED)
+    b = lbm.Simulation(wl, phi0)
+    batch = lbm.Batch(max_jobs=2)
+    a.step(7)
+    batch.step([a], [5])
+    b.step(12)
+    for f in (lbm.FIELD_N, lbm.FIELD_PHI, lbm.FIELD_B):
+        err = float(np.max(np.abs(a.read(f) - b.read(f))) / np.max(np.abs(b.read(f))))
+        print(f"[batch] after collide-colour {W.PRECISION_NAMES[prec]} field {f}: {err:.2e}", flush=True)
+        assert err < (1e-6 if prec == W.FP32 else 1e-4), f
+    assert a.observe()["nonfinite"] == 0
+    batch.close()
+    a.close()
+    b.close()
+
+
 def test_batch_rejects_sparse_layout():
     """Contexts in the fluid-only layout step alone: lbm_batch_step refuses them."""
     lbm = _lbm()
@@ -155,3 +182,49 @@ def test_batch_rejects_sparse_layout():
     batch.close()
     a.close()
     b.close()
+
+
+def test_served_mix_isolates_a_non_finite_run():
+    """Failure isolation in serving: one request of a small mix has a NaN
+    written into its populations (from the host, through lbm_set_field) when
+    it is prepared.  The mix still completes; that run is retired with status
+    "unstable" at the first check, and every other run ends in exactly the
+    state it reaches alone (bit for bit)."""
+    lbm = _lbm()
+    from paper_2605_30878_amd import serve
+
+    reqs = serve.mixed_requests(10, seed=5, step_scale=0.01, size_scale=0.3, precision=W.FP32)
+    reqs = serve.poisson_arrivals(reqs, rate=200.0, seed=6)
+    victim = 8   # a D3Q19 run of 191 steps: several 40-step ticks
+
+    class PoisonServer(serve.Server):
+        def _prepare(self, r):
+            sim = super()._prepare(r)
+            if r.rid == victim:
+                N = sim.read(lbm.FIELD_N)
+                fluid = np.flatnonzero((sim.read(lbm.FIELD_FLAGS).astype(np.int64) & lbm.FLAG_SOLID) == 0)
+                N[3, fluid[len(fluid) // 2]] = np.nan
+                sim.set_field(lbm.FIELD_N, N)
+            return sim
+
+    srv = PoisonServer(hbm_budget=8e9, max_slots=6, tick_steps=40, keep_state=True, check_ticks=1)
+    res = srv.run(reqs)
+    srv.close()
+    summ = serve.summarize(res, max(r.finished for r in res))
+    print(f"[serve] with a poisoned run: {summ}", flush=True)
+    assert len(res) == len(reqs)
+    by_id = {r.rid: r for r in res}
+    assert by_id[victim].status == "unstable" and by_id[victim].obs["nonfinite"] > 0
+    assert by_id[victim].steps < reqs[victim].steps      # retired before its last step
+    assert summ["unstable_jobs"] == 1 and summ["jobs"] == len(reqs) - 1
+    for r in res:
+        if r.rid == victim:
+            continue
+        assert r.status == "ok" and r.obs["nonfinite"] == 0 and r.steps == reqs[r.rid].steps
+        wl = reqs[r.rid].workload
+        s = lbm.Simulation(wl, W.initial_phi(wl))
+        s.step(r.steps)
+        for f, key in ((lbm.FIELD_N_OFFSET, "N"), (lbm.FIELD_B, "B")):
+            err, ok = _close(r.state[key], s.read(f), wl.precision)
+            assert ok, (wl.name, key, err)
+        s.close()

@@ -2,13 +2,20 @@
 1000, viscosity ratio 100) against the FP64 oracle after 20000 steps: the
 contact angle (from the apex height and liquid volume, Section 3.2's
 measure) within 0.5 degrees, the spurious-current maximum within 10 %, the
-Laplace pressure jump within 2 % for FP32 and FP16-offset storage.  BF16
-offsets (8 significant bits) miss that bar at this density ratio (measured
--0.62 degrees at 90 and -1.62 degrees at 150, +14 % and +17 % spurious
-currents): they are reported, not recommended, and held to 2 degrees, 25 %
-and 2 % only so that a regression still shows.  The oracle's numbers are in
-tests/golden/sphere64_oracle.json, written by tests/golden/make_sphere64.py
-(oracle only); the same FP64 measurement is applied to both."""
+Laplace pressure jump within 2 % for FP32 and FP16-offset storage.
+
+Two starts, two stored oracle references (tests/golden/, written by
+tests/golden/make_sphere64.py from the oracle alone; the same FP64
+measurement is applied to both sides):
+  - the equilibrium cap of each angle (Sec. 3.2's start;
+    sphere64_eq_oracle.json): the state at 20000 steps is the equilibrium
+    drop, so this compares equilibrium angles;
+  - a drop of radius 10 on the sphere top (sphere64_oracle.json), still
+    relaxing at 20000 steps: this compares trajectories.
+BF16 offsets (8 significant bits) miss the bar in the transient at this
+density ratio (measured -0.62 degrees at 90 and -1.62 degrees at 150, +14 %
+and +17 % spurious currents): for the transient they are held to 2 degrees,
+25 % and 2 % only as a regression guard, not as a claim."""
 import json
 import os
 
@@ -20,13 +27,19 @@ from paper_2605_30878_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "sphere64_oracle.json")
+GOLDEN_DIR = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+GOLDEN = {"transient": os.path.join(GOLDEN_DIR, "sphere64_oracle.json"),
+          "equilibrium": os.path.join(GOLDEN_DIR, "sphere64_eq_oracle.json")}
+
+# (angle, spurious current, Laplace jump) bars per storage and start
+BARS = {"transient": {"f32": (0.5, 0.10, 0.02), "f16ofs": (0.5, 0.10, 0.02), "bf16ofs": (2.0, 0.25, 0.02)},
+        "equilibrium": {"f32": (0.5, 0.10, 0.02), "f16ofs": (0.5, 0.10, 0.02), "bf16ofs": (0.5, 0.10, 0.02)}}
 
 
-def _golden():
-    if not os.path.exists(GOLDEN):
+def _golden(start):
+    if not os.path.exists(GOLDEN[start]):
         return {}
-    with open(GOLDEN) as f:
+    with open(GOLDEN[start]) as f:
         return json.load(f)
 
 
@@ -48,12 +61,19 @@ def _measure(lbm, sim, wl):
             "max_speed": o["max_speed"], "mass_blue": o["mass_blue"]}
 
 
-def test_reduced_precision_contact_angle_against_oracle():
+def _workload(start, theta, prec, steps, probe):
+    if start == "equilibrium":
+        return W.sphere_cap_d3q19(64, theta=theta, precision=prec, probe=probe, steps=steps)
+    return W.sphere_d3q19(64, theta=theta, precision=prec, steps=steps).with_(probe=probe)
+
+
+@pytest.mark.parametrize("start", ["equilibrium", "transient"])
+def test_reduced_precision_contact_angle_against_oracle(start):
     import torch
 
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
-    gold = _golden()
+    gold = _golden(start)
     if not gold:
         pytest.skip("no oracle reference yet")
     from paper_2605_30878_amd import lbm
@@ -62,9 +82,9 @@ def test_reduced_precision_contact_angle_against_oracle():
     precs = [W.FP32, W.FP16_OFS, W.BF16_OFS]
     cases = [(k, p) for k in keys for p in precs]
     steps = int(gold[keys[0]]["steps"])
-    print(f"[angle] cases={cases} steps={steps}", flush=True)
-    wls = [W.sphere_d3q19(64, theta=gold[k].get("theta", float(k.split("/")[0])), precision=p,
-                          steps=steps).with_(probe=int(gold[k].get("probe", 0))) for k, p in cases]
+    print(f"[angle] start={start} cases={cases} steps={steps}", flush=True)
+    wls = [_workload(start, gold[k].get("theta", float(k.split("/")[0])), p, steps, int(gold[k].get("probe", 0)))
+           for k, p in cases]
     sims = [lbm.Simulation(wl, W.initial_phi(wl)) for wl in wls]
     batch = lbm.Batch(max_jobs=len(sims))
     for _ in range(steps // 2000):
@@ -79,12 +99,12 @@ def test_reduced_precision_contact_angle_against_oracle():
         r_dp = m["dp_h"] / g["dp_h"] - 1.0
         r_mass = m["mass_blue"] / g["mass_blue"] - 1.0
         name = W.PRECISION_NAMES[p]
-        print(f"[angle] theta={t} {name}: theta {m['theta_apex']:.3f} (oracle {g['theta_apex']:.3f}, "
+        print(f"[angle] {start} theta={t} {name}: theta {m['theta_apex']:.3f} (oracle {g['theta_apex']:.3f}, "
               f"diff {d_theta:+.3f}); max|u| {m['max_speed']:.3e} ({r_speed:+.2%}); "
               f"dp_h {m['dp_h']:.4e} ({r_dp:+.2%}); mass {r_mass:+.2e}", flush=True)
         worst[(t, name)] = (d_theta, r_speed, r_dp)
         sim.close()
-    bars = {"f32": (0.5, 0.10, 0.02), "f16ofs": (0.5, 0.10, 0.02), "bf16ofs": (2.0, 0.25, 0.02)}
+    bars = BARS[start]
     for (t, name), (d_theta, r_speed, r_dp) in worst.items():
         b_theta, b_speed, b_dp = bars[name]
         assert abs(d_theta) <= b_theta, (t, name, d_theta)

@@ -1,7 +1,8 @@
 """The benchmark workloads at their full size, in the launch configurations
-the benchmark times: the D3Q19 256^3 drop on a sphere (density ratio 1000,
-tiled colour kernel, row collide-stream kernel) in FP32 and in FP16-offset
-storage, and the 384^3 sphere packing in the fluid-only layout.  The oracle cannot
+the benchmark times: the D3Q19 256^3 drop on a sphere (density ratio 1000)
+in FP32 and in FP16-offset storage, both in the two-pass form (tiled colour
+kernel, row collide-stream kernel) and in the collide-colour form, and the
+384^3 sphere packing in the fluid-only layout.  The oracle cannot
 run this box end to end in a test, so it checks sampled nodes one by one
 with its own per-node functions, in FP64, from the library's state read
 back (which FP32 holds exactly in FP64):
@@ -53,6 +54,11 @@ CASES = {
     # 16-bit offsets: tolerances from the FP16 spacing of the largest stored
     # offset (computed below)
     "sphere256_fp16ofs": (lambda: W.sphere_d3q19(256, theta=60.0, precision=W.FP16_OFS), 0, (None, None, 5e-7), True),
+    # the collide-colour form (LBM_OPT_FUSED), which the benchmark times
+    "sphere256_f32_collide_colour": (lambda: W.sphere_d3q19(256, theta=60.0, precision=W.FP32), 1,
+                                     (1e-7, 1e-6, 5e-7), True),
+    "sphere256_fp16ofs_collide_colour": (lambda: W.sphere_d3q19(256, theta=60.0, precision=W.FP16_OFS), 1,
+                                         (None, None, 5e-7), True),
     # the porous workload in the fluid-only layout (its ghost rule, the
     # fluid-only probe, is checked against the oracle on smaller packings)
     "porous384_sparse_f32": (lambda: W.porous_d3q19(384, precision=W.FP32), 32, (1e-7, 1e-6, None), False),

@@ -100,6 +100,15 @@ def test_poisson_arrivals_and_summary():
     assert s["jobs"] == 100 and s["throughput_jobs_s"] == 2.0
     assert s["p50_latency_s"] == pytest.approx(50.5) and s["p99_latency_s"] == pytest.approx(99.01)
     assert s["aggregate_mlups"] == pytest.approx(100 * 100 * 10 / 50.0 / 1e6)
+    # unstable runs (retired early) stay out of the latency and job counts;
+    # the updates they made still count in the aggregate rate
+    res[3].status = "unstable"
+    res[7].status = "unstable"
+    s = serve.summarize(res, wall=50.0)
+    assert s["jobs"] == 98 and s["unstable_jobs"] == 2 and s["throughput_jobs_s"] == pytest.approx(98 / 50.0)
+    assert s["aggregate_mlups"] == pytest.approx(100 * 100 * 10 / 50.0 / 1e6)
+    lat = np.array([r.latency for r in res if r.status == "ok"])
+    assert s["p99_latency_s"] == pytest.approx(float(np.percentile(lat, 99)))
 
 
 def test_lens_geometry_by_monte_carlo():
