@@ -255,6 +255,21 @@ int lbm_step_profiled(lbm_ctx* ctx, int64_t nsteps, double* ms_out);
 /* Reduce the diagnostics on the device and copy them out (synchronises).
  * Returns LBM_EUNSTABLE (and fills *out) if any value is non-finite. */
 int lbm_observe(lbm_ctx* ctx, lbm_obs* out);
+/* lbm_observe for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same diagnostics, bit for bit, with the reduction's scratch (1024
+ * per-block partials, the non-finite counters and the result, 74 KB) in a
+ * static device array of the library instead of the bound buffer.  The
+ * array holds no per-node data, so every box size fits it.  Each device
+ * holds one copy, shared by every context on it and kept between calls:
+ * every call overwrites all of it before reading it, and calls that overlap
+ * on one device (contexts on different threads or streams) race.  Its
+ * address is looked up once per device at the first call there (the device
+ * of the bound buffer); the call makes no allocation.  Synchronises the
+ * bound stream.  Errors as lbm_observe, and LBM_EHIP if the address lookup
+ * fails. */
+int lbm_observe_static(lbm_ctx* ctx, lbm_obs* out);
+
 
 /* Copy a field to the host as FP64 (`count` doubles; synchronises).  Solid
  * nodes read u = p = 0 and N = B = 0. */

@@ -31,6 +31,7 @@ struct lbm_ctx {
     int64_t n_solid = 0;
     size_t need = 0;
     char* base = nullptr;
+    int device = 0;       // device of the bound buffer
     hipStream_t stream = nullptr;
     DevState d{};
     int cur = 0;   // population / compact-record buffer holding the state
@@ -548,6 +549,7 @@ int lbm_bind(lbm_ctx* c, void* dev, size_t bytes, void* stream) {
         return fail(c, LBM_EINVAL, "buffer is not device memory");
     }
     c->base = (char*)dev;
+    c->device = attr.device;
     c->stream = (hipStream_t)stream;
     const int Q = c->Q, NC = c->NC;
     const int64_t ng = (int64_t)c->g_node.size();
@@ -830,19 +832,12 @@ int lbm_step_profiled(lbm_ctx* c, int64_t nsteps, double* ms_out) {
     return rc;
 }
 
-int lbm_observe(lbm_ctx* c, lbm_obs* out) {
-    if (!c || !out) return LBM_EINVAL;
-    if (!c->started) return fail(c, LBM_ESTATE, "set PHI before observing");
-    const int lat = (int)c->P.lattice;
-    const uint32_t prec = c->P.precision;
-    HIPCHK(c, launch_colour(lat, prec, c->d, c->sp, c->cur, c->ps, c->liq, c->stream), "colour");
-    HIPCHK(c, launch_macro(lat, prec, c->d, c->sp, c->cur, c->ps, c->stream), "macro");
-    const ReduceScratch rs{c->d.partial, c->d.nonfinite, c->d.result};
-    HIPCHK(c, launch_reduce(lat, prec, c->d, c->sp, c->cur, c->ps, c->liq, rs, c->stream), "reduce");
+// Copy the reduced diagnostics out of rs (synchronises) into *out.
+static int finish_observe(lbm_ctx* c, const ReduceScratch& rs, lbm_obs* out) {
     double r[8];
     int64_t nf = 0;
-    HIPCHK(c, hipMemcpyAsync(r, c->d.result, 8 * 8, hipMemcpyDeviceToHost, c->stream), "download");
-    HIPCHK(c, hipMemcpyAsync(&nf, c->d.nonfinite + REDUCE_BLOCKS, 8, hipMemcpyDeviceToHost, c->stream), "download");
+    HIPCHK(c, hipMemcpyAsync(r, rs.result, 8 * 8, hipMemcpyDeviceToHost, c->stream), "download");
+    HIPCHK(c, hipMemcpyAsync(&nf, rs.nonfinite + REDUCE_BLOCKS, 8, hipMemcpyDeviceToHost, c->stream), "download");
     HIPCHK(c, hipStreamSynchronize(c->stream), "sync");
     std::memset(out, 0, sizeof(*out));
     out->step = c->step;
@@ -859,6 +854,31 @@ int lbm_observe(lbm_ctx* c, lbm_obs* out) {
     out->kinetic_energy = r[6];
     if (nf > 0) return fail(c, LBM_EUNSTABLE, "non-finite values in the state");
     return LBM_OK;
+}
+
+int lbm_observe(lbm_ctx* c, lbm_obs* out) {
+    if (!c || !out) return LBM_EINVAL;
+    if (!c->started) return fail(c, LBM_ESTATE, "set PHI before observing");
+    const int lat = (int)c->P.lattice;
+    const uint32_t prec = c->P.precision;
+    HIPCHK(c, launch_colour(lat, prec, c->d, c->sp, c->cur, c->ps, c->liq, c->stream), "colour");
+    HIPCHK(c, launch_macro(lat, prec, c->d, c->sp, c->cur, c->ps, c->stream), "macro");
+    const ReduceScratch rs{c->d.partial, c->d.nonfinite, c->d.result};
+    HIPCHK(c, launch_reduce(lat, prec, c->d, c->sp, c->cur, c->ps, c->liq, rs, c->stream), "reduce");
+    return finish_observe(c, rs, out);
+}
+
+int lbm_observe_static(lbm_ctx* c, lbm_obs* out) {
+    if (!c || !out) return LBM_EINVAL;
+    if (!c->started) return fail(c, LBM_ESTATE, "set PHI before observing");
+    const int lat = (int)c->P.lattice;
+    const uint32_t prec = c->P.precision;
+    ReduceScratch rs;
+    HIPCHK(c, static_reduce_scratch(c->device, rs), "static scratch address");
+    HIPCHK(c, launch_colour(lat, prec, c->d, c->sp, c->cur, c->ps, c->liq, c->stream), "colour");
+    HIPCHK(c, launch_macro(lat, prec, c->d, c->sp, c->cur, c->ps, c->stream), "macro");
+    HIPCHK(c, launch_reduce(lat, prec, c->d, c->sp, c->cur, c->ps, c->liq, rs, c->stream), "reduce");
+    return finish_observe(c, rs, out);
 }
 
 // One FP64 plane of aux to `count` = n box values (scattered from slot

@@ -42,6 +42,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <type_traits>
 #include <utility>
 
@@ -1937,6 +1938,43 @@ hipError_t launch_macro(int lattice, uint32_t prec, const DevState& d, const Ste
 hipError_t launch_reduce(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
                          int liq, const ReduceScratch& rs, hipStream_t st) {
     LBM_DISPATCH(reduce_t, d, p, cur, ps, liq, rs, st);
+}
+
+// Scratch of the diagnostics in device memory of the library's own, for
+// callers that cannot allocate (lbm_observe_static): the reduction partials,
+// the non-finite counters and the result.  Each device holds one copy; in
+// host code `scratch` names no device address, so its address is taken with
+// hipGetSymbolAddress once per device (device current) and kept.
+constexpr size_t SCRATCH_PARTIAL = (size_t)REDUCE_BLOCKS * 8 * sizeof(double);
+constexpr size_t SCRATCH_COUNTS = ((size_t)(REDUCE_BLOCKS + 1) * sizeof(int64_t) + 255) / 256 * 256;
+constexpr size_t SCRATCH_BYTES = SCRATCH_PARTIAL + SCRATCH_COUNTS + 256;
+static __device__ __align__(256) unsigned char scratch[SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_addr[MAX_DEVICES] = {};
+
+hipError_t static_reduce_scratch(int device, ReduceScratch& out) {
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_addr[device]) {
+        int prev = 0;
+        hipError_t e = hipGetDevice(&prev);
+        if (e != hipSuccess) return e;
+        if (prev != device && (e = hipSetDevice(device)) != hipSuccess) return e;
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (prev != device) {
+            const hipError_t e2 = hipSetDevice(prev);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        g_scratch_addr[device] = ptr;
+    }
+    unsigned char* base = (unsigned char*)g_scratch_addr[device];
+    out.partial = (double*)base;
+    out.nonfinite = (int64_t*)(base + SCRATCH_PARTIAL);
+    out.result = (double*)(base + SCRATCH_PARTIAL + SCRATCH_COUNTS);
+    return hipSuccess;
 }
 hipError_t launch_init(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
                        hipStream_t st) {

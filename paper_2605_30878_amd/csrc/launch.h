@@ -99,6 +99,10 @@ struct ReduceScratch {
 // Diagnostics into rs (after launch_macro).
 hipError_t launch_reduce(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,
                          int liq, const ReduceScratch& rs, hipStream_t stream);
+// The library's own reduction scratch on `device` (a static device array;
+// its address is looked up once per device).
+constexpr int MAX_DEVICES = 64;
+hipError_t static_reduce_scratch(int device, ReduceScratch& out);
 // Start of a run from the FP64 phi in aux[0]: N = chi, B = phi chi at fluid
 // nodes, phi of solid nodes (both buffers) = phi_solid.
 hipError_t launch_init(int lattice, uint32_t prec, const DevState& d, const StepParams& p, int cur, int ps,

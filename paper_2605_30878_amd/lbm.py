@@ -31,7 +31,8 @@ FLAG_SOLID, FLAG_NEAR_SOLID, FLAG_GHOST = 1, 2, 4
 EXPORTED = ["lbm_create", "lbm_set_geometry", "lbm_device_bytes", "lbm_bind", "lbm_set_wetting",
             "lbm_set_field", "lbm_step", "lbm_step_profiled", "lbm_observe", "lbm_read_field",
             "lbm_lattice", "lbm_destroy", "lbm_last_error", "lbm_batch_table_bytes", "lbm_batch_create",
-            "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_last_error", "lbm_hbm_probe"]
+            "lbm_batch_step", "lbm_batch_destroy", "lbm_batch_last_error", "lbm_hbm_probe",
+            "lbm_observe_static"]
 
 
 class LbmError(RuntimeError):
@@ -84,6 +85,7 @@ def load_library(path: str = LIB_PATH):
     lib.lbm_step.argtypes = [vp, C.c_int64]
     lib.lbm_step_profiled.argtypes = [vp, C.c_int64, dp]
     lib.lbm_observe.argtypes = [vp, C.POINTER(lbm_obs)]
+    lib.lbm_observe_static.argtypes = [vp, C.POINTER(lbm_obs)]
     lib.lbm_read_field.argtypes = [vp, C.c_int, dp, C.c_size_t]
     lib.lbm_lattice.argtypes = [C.c_uint32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     lib.lbm_destroy.argtypes = [vp]
@@ -230,9 +232,13 @@ class Simulation:
             return out.reshape(3, self.n)
         return out
 
-    def observe(self, allow_unstable: bool = False) -> Dict[str, object]:
+    def observe(self, allow_unstable: bool = False, static_scratch: bool = False) -> Dict[str, object]:
+        """Diagnostics (lbm_observe); with static_scratch, through
+        lbm_observe_static, whose reduction scratch is the library's own
+        static device array (no caller-provided workspace)."""
         o = lbm_obs()
-        rc = self.lib.lbm_observe(self._h, C.byref(o))
+        fn = self.lib.lbm_observe_static if static_scratch else self.lib.lbm_observe
+        rc = fn(self._h, C.byref(o))
         if rc != OK and not (allow_unstable and rc == EUNSTABLE):
             self._check(rc)
         return {"step": o.step, "n_fluid": o.n_fluid, "n_solid": o.n_solid, "n_ghost": o.n_ghost,
