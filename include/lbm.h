@@ -60,8 +60,8 @@ enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_OFS = 2, LBM_BF16_OFS = 3 };
 /* Step forms.  By default every step is three launches: colour field
  * (phi = sum_i B_i, Eq. A13, from N and the compact record of the last
  * collide), ghost update (Eq. 9), and the collide-stream kernel.  With
- * LBM_OPT_FUSED, D3Q19 boxes with n[0] % 64 == 0 and n[1] % 8 == 0 run
- * every step as the ghost update, one collide kernel over 64 x 8 columns
+ * LBM_OPT_FUSED, D3Q19 boxes with n[0] % 64 == 0 and n[1] % 8 == 0 whose
+ * 19 population planes take at most 4 GiB run every step as the ghost update, one collide kernel over 64 x 8 columns
  * that also forms the next step's phi from the recoloured populations it
  * streams (Eq. A12, A17), and a small launch that adds the values crossing
  * a column's faces.  N is then read once per step instead of twice, and no

@@ -90,6 +90,9 @@ static size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 // take the collide-colour form).
 static size_t fused_cross_bytes(const lbm_ctx* c) {
     if (!(c->P.options & LBM_OPT_FUSED) || c->sparse) return 0;
+    // the collide-colour kernel addresses all Q population planes with one
+    // 32-bit byte offset from the buffer's base
+    if ((uint64_t)c->Q * (uint64_t)c->S * elem_size(c->P.precision) > 0xFFFFFFFFull) return 0;
     return cross_bytes((int)c->P.lattice, c->P.precision, c->sp);
 }
 

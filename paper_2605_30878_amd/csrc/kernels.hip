@@ -82,6 +82,16 @@ __device__ __forceinline__ V ld_nt(const V* __restrict__ base, uint32_t idx) {
     return __builtin_nontemporal_load(
         reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + idx * (uint32_t)sizeof(V)));
 }
+// Element e of a multi-plane array through one 32-bit byte offset from the
+// array's base (e = plane * S + node): one wave-uniform base for every
+// plane, so a kernel that marches through many planes keeps one scalar
+// pointer instead of one per plane.  The caller guarantees that the whole
+// array is below 4 GiB.
+template <class V>
+__device__ __forceinline__ V ld_nt_e(const V* __restrict__ base, uint32_t e) {
+    return __builtin_nontemporal_load(
+        reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + e * (uint32_t)sizeof(V)));
+}
 template <class V>
 __device__ __forceinline__ void st(V* __restrict__ base, uint32_t idx, V v) {
     *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(V)) = v;
@@ -135,6 +145,8 @@ struct KParams {
     T sigma, W, inv_W;
     T g[3];
     T chi[Q];
+    T chi_a, chi_d;         // chi_i of the axis (w_1) and the diagonal (w_Q-1) directions: chi_i = (1 - alpha)
+                            // w_i / (1 - w_0) takes one value per weight class, so kernels name 3 values, not Q
     T n_thresh2;            // |grad phi|^2 below which n_phi = 0
     T n_s, n_inv_s;         // 16-bit storage scale of N and its inverse
     T n_close;              // target of the closure sum in "off" space: (1 - sum chi) / s
@@ -158,6 +170,8 @@ static KParams<T, L::Q> make_kparams(const StepParams& p) {
     k.inv_W = T(1.0 / p.W);
     for (int a = 0; a < 3; a++) k.g[a] = T(L::D == 2 && a == 2 ? 0.0 : p.g[a]);
     for (int i = 0; i < L::Q; i++) k.chi[i] = T(p.chi[i]);
+    k.chi_a = T(p.chi[1]);
+    k.chi_d = T(p.chi[L::Q - 1]);
     // |grad phi| > 1e-12 (FP64) or > 1e-7 (FP32) defines the interface normal
     k.n_thresh2 = std::is_same<T, double>::value ? T(1e-24) : T(1e-14);
     const double scale = NStore<T, SN>::scaled ? N16_SCALE : 1.0;
@@ -472,7 +486,8 @@ __device__ __forceinline__ T compact_term(T n, T phi_src, T gx, T gy, T gz, T p,
     if constexpr (cy != 0) cG += cmul<cy>(gy);
     if constexpr (cz != 0) cG += cmul<cz>(gz);
     const T sG = sgn * cG;
-    return (phi_src + sG) * P.chi[I] + phi_src * n + sG * (wi * T(3) * p);
+    const T chi = L::w[I] == L::w[1] ? P.chi_a : P.chi_d;   // equals P.chi[I] (one value per weight class)
+    return (phi_src + sG) * chi + phi_src * n + sG * (wi * T(3) * p);
 }
 
 // Post-stream liquid population B_i(y) from the compact record.  nb[i] is
@@ -894,13 +909,55 @@ struct CrossGeom {
     int nzc;       // z-chunks
 };
 
-// Lateral face-crossing values of one plane, staged in LDS by source
-// position and copied to the inbox after the barrier (coalesced, by all
-// threads, instead of by the few edge lanes of each wave): the x ring holds
-// the five directions leaving through each x face ([2][5][KTY], by source
-// y), the y ring the five leaving through each y face without leaving
-// through an x face ([2][5][KTX], by source x).
-constexpr int XRING = 2 * 5 * KTY, YRING = 2 * 5 * KTX;
+// Lateral face-crossing values of one plane are staged in LDS and copied to
+// the inbox after the barrier by all threads, coalesced, instead of by the
+// few edge lanes of each wave: values leaving through an x face land in two
+// halo columns of the hand-over array (so that every lane of a wave stores
+// to LDS unconditionally), values leaving through a y face in a y ring
+// ([2 faces][5 directions][KTX + 2 target x]; only the two edge rows of the
+// tile, each a whole wave, store there).
+constexpr int KHX = KTX + 2;                 // hand-over row: the tile and two halo columns
+constexpr int YRING = 2 * 5 * KHX;
+constexpr int XHALO = 2 * 5 * KTY;           // copy-out entries of the halo columns
+
+// Direction pairs leaving through the faces normal to axis A: pair
+// p = side 5 + k is the k-th direction (ascending) with c_A = -1 (side 0)
+// or +1 (side 1).  Bit-packed per pair: the direction (5 bits), the other
+// components + 1 (2 bits each) and, for A = 1, the direction's index among
+// those with its c_x (3 bits; the k of its x-face slot).
+constexpr int face_dir(int A, int p) {
+    int k = p % 5;
+    const int S = p / 5 ? 1 : -1;
+    for (int i = 0; i < 19; i++)
+        if (LatD3Q19::c[i][A] == S && k-- == 0) return i;
+    return -1;
+}
+constexpr int index_among(int i, int A) {
+    int k = 0;
+    for (int j = 0; j < i; j++)
+        if (LatD3Q19::c[j][A] == LatD3Q19::c[i][A]) k++;
+    return k;
+}
+template <int A>
+struct FaceTab {
+    static constexpr uint64_t pack_dir() {
+        uint64_t v = 0;
+        for (int p = 0; p < 10; p++) v |= (uint64_t)face_dir(A, p) << (5 * p);
+        return v;
+    }
+    static constexpr uint32_t pack_comp(int B) {
+        uint32_t v = 0;
+        for (int p = 0; p < 10; p++) v |= (uint32_t)(LatD3Q19::c[face_dir(A, p)][B] + 1) << (2 * p);
+        return v;
+    }
+    static constexpr uint32_t pack_kx() {
+        uint32_t v = 0;
+        for (int p = 0; p < 10; p++) v |= (uint32_t)index_among(face_dir(A, p), 0) << (3 * p);
+        return v;
+    }
+    static constexpr uint64_t DIR = pack_dir();
+    static constexpr uint32_t CX = pack_comp(0), CY = pack_comp(1), CZ = pack_comp(2), KX = pack_kx();
+};
 
 // Target tile-chunk (absolute inbox offset of its block) and local z of a
 // value leaving plane lz of chunk bz along c_z = cz (the same chunk unless
@@ -929,25 +986,26 @@ __global__ __launch_bounds__(KNT, sizeof(T) == 8 ? 2 : 4) void k_collide_colour(
     using L = LatD3Q19;
     using NS = NStore<T, SN>;
     constexpr int Q = 19;
-    __shared__ T xch[2][Q - 1][KTY][KTX];   // [iteration parity][direction - 1][target y][target x]
-    __shared__ T ring[2][XRING + YRING];     // [iteration parity] the plane's lateral face-crossing values
+    __shared__ T xch[2][Q - 1][KTY][KHX];   // [iteration parity][direction - 1][target y][target x + 1]
+    __shared__ T ring[2][YRING];             // [iteration parity] values leaving through a y face
     int bx, by, bz;
     tile_index(ts, bx, by, bz);
     const int x0 = bx * KTX, y0 = by * KTY, z0 = bz * cg.zc;
     const int z1 = min(z0 + cg.zc, P.nz), zlen = z1 - z0;
-    const int tx = threadIdx.x % KTX, ty = threadIdx.x / KTX;
+    static_assert(KTX == 64, "one tile row per wave: the row index is wave-uniform");
+    const int tx = threadIdx.x % KTX;
+    const int ty = __builtin_amdgcn_readfirstlane(threadIdx.x / KTX);
     const int ix = x0 + tx, iy = y0 + ty;
-    const int64_t S = P.S;
+    const uint32_t S32 = (uint32_t)P.S;   // plane stride; Q planes of N fit in 4 GiB (checked on the host)
     const int64_t tvals = cross_tile_vals(cg.zc);
     const uint32_t plane = (uint32_t)P.nx * (uint32_t)P.ny;
     const uint32_t xy = (uint32_t)ix + (uint32_t)P.nx * (uint32_t)iy;
-    // per thread, fixed for the whole march: bit i of lat_out is set when
-    // x + c_i leaves the tile laterally, bit i of lat_in when x - c_i lies in it
-    uint32_t lat_out = 0, lat_in = 0;
+    // per thread, fixed for the whole march: bit i of lat_in is set when
+    // x - c_i lies in the tile
+    uint32_t lat_in = 0;
     static_for<1, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int cx = L::c[i][0], cy = L::c[i][1];
-        if (tx + cx < 0 || tx + cx >= KTX || ty + cy < 0 || ty + cy >= KTY) lat_out |= 1u << i;
         if (tx - cx >= 0 && tx - cx < KTX && ty - cy >= 0 && ty - cy < KTY) lat_in |= 1u << i;
     });
     // neighbour offsets in x and y (periodic wrap at the box faces)
@@ -985,7 +1043,7 @@ __global__ __launch_bounds__(KNT, sizeof(T) == 8 ? 2 : 4) void k_collide_colour(
             };
             T N[Q], ph[Q];
 #pragma unroll
-            for (int i = 0; i < Q; i++) N[i] = NS::dec(ld_nt(Nsrc + (int64_t)i * S, x), P.n_s);
+            for (int i = 0; i < Q; i++) N[i] = NS::dec(ld_nt_e(Nsrc, (uint32_t)i * S32 + x), P.n_s);
             ph[0] = ld(phi, x);
             uint32_t bbm = 0;   // bit i: x + c_i is solid (bounce-back link)
             const bool near = (f & FLAG_NEAR_SOLID) != 0;
@@ -1017,30 +1075,29 @@ __global__ __launch_bounds__(KNT, sizeof(T) == 8 ? 2 : 4) void k_collide_colour(
                 const T b = compact_term<L, T, i>(NS::dec(e[i], P.n_s), mc.phi, G[0], G[1], G[2], mc.p, T(1), P);
                 if ((bbm >> i) & 1u) {
                     // bounce-back: N*_i and B*_i return to x in direction opp(i)
-                    st(Ndst + (int64_t)j * S, x, e[i]);
+                    st(Ndst, (uint32_t)j * S32 + x, e[i]);
                     m |= 1u << j;
-                    if constexpr (L::c[j][2] == 0) xch[buf][j - 1][ty][tx] = b;   // its source is solid: slot free
+                    if constexpr (L::c[j][2] == 0) xch[buf][j - 1][ty][tx + 1] = b;   // its source is solid: slot free
                     else if constexpr (L::c[j][2] > 0) bbu[j - 9] = b;
-                    else xch[buf ^ 1][j - 1][ty][tx] = b;   // read back with the plane above (own slot)
+                    else xch[buf ^ 1][j - 1][ty][tx + 1] = b;   // read back with the plane above (own slot)
                 } else {
-                    st(Ndst + (int64_t)i * S, nbr(ic), e[i]);
-                    if ((lat_out >> i) & 1u) {
-                        // leaves the tile through a lateral face: staged in the ring
-                        if (tx + cx < 0 || tx + cx >= KTX) {
-                            if constexpr (cx != 0) ring[buf][((cx > 0 ? 5 : 0) + cross_k<i, 0, cx>()) * KTY + ty] = b;
-                        } else {
-                            if constexpr (cy != 0)
-                                ring[buf][XRING + ((cy > 0 ? 5 : 0) + cross_k<i, 1, cy>()) * KTX + tx] = b;
-                        }
-                    } else if ((cz > 0 && lz + 1 == zlen) || (cz < 0 && lz == 0)) {
-                        // leaves the chunk through its top or bottom plane (the
-                        // whole workgroup takes this branch together)
+                    st(Ndst, (uint32_t)i * S32 + nbr(ic), e[i]);
+                    // the branches on ty and lz are wave-uniform
+                    const bool y_out = cy != 0 && (ty + cy < 0 || ty + cy >= KTY);
+                    const bool z_out = cz != 0 && (lz + cz < 0 || lz + cz >= zlen);
+                    if (y_out) {
+                        // leaves through a y face (the whole wave of an edge row)
+                        if constexpr (cy != 0) ring[buf][((cy > 0 ? 5 : 0) + cross_k<i, 1, cy>()) * KHX + tx + cx + 1] = b;
+                    } else if (z_out && (cx == 0 || (tx + cx >= 0 && tx + cx < KTX))) {
+                        // leaves the chunk through its bottom or top plane, not through
+                        // an x face (the whole workgroup on those two planes)
                         int tbz, tz, tzlen;
                         cross_target_z(cg, P.nz, bz, zlen, lz, cz, tbz, tz, tzlen);
                         const int64_t t = ((int64_t)tbz * cg.yt + by) * cg.xt + bx;
                         cross[t * tvals + cross_slot<i>(tx + cx, ty + cy, tz, cg.zc, tzlen)] = b;
                     } else {
-                        xch[buf][i - 1][ty + cy][tx + cx] = b;
+                        // stays in the tile, or leaves through an x face (halo column)
+                        xch[buf][i - 1][ty + cy][tx + cx + 1] = b;
                     }
                 }
             });
@@ -1050,65 +1107,76 @@ __global__ __launch_bounds__(KNT, sizeof(T) == 8 ? 2 : 4) void k_collide_colour(
         // overwrites that buffer only after it)
         T upv[5];
 #pragma unroll
-        for (int k = 0; k < 5; k++) upv[k] = lz > 0 ? xch[buf ^ 1][9 + k - 1][ty][tx] : T(0);
+        for (int k = 0; k < 5; k++) upv[k] = lz > 0 ? xch[buf ^ 1][9 + k - 1][ty][tx + 1] : T(0);
         __syncthreads();
-        // the ring's values to the inbox of the tile they enter (entries of
-        // solid or bounce-back sources hold stale values; the fix-up reads
-        // only entries of fluid sources)
-        for (int k = threadIdx.x; k < XRING + YRING; k += KNT) {
-            const T v = ring[buf][k];
-            if (k < XRING) {
-                const int pr = k / KTY, sy = k % KTY;     // pair (side, direction), source y
-                static_for<0, 10>([&](auto pc) {
-                    constexpr int pp = decltype(pc)::value;
-                    constexpr int side = pp / 5, kk = pp % 5;
-                    constexpr int i = L::dir_with<0, side ? 1 : -1>(kk);
-                    constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-                    if (pr == pp) {
-                        const int sx = cx > 0 ? KTX - 1 : 0;
-                        int ttx = sx + cx, tty = sy + cy, tbx, tby = by;
-                        tbx = cx > 0 ? (bx == cg.xt - 1 ? 0 : bx + 1) : (bx == 0 ? cg.xt - 1 : bx - 1);
-                        ttx -= cx > 0 ? KTX : -KTX;
-                        if (tty < 0) { tty += KTY; tby = by == 0 ? cg.yt - 1 : by - 1; }
-                        if (tty >= KTY) { tty -= KTY; tby = by == cg.yt - 1 ? 0 : by + 1; }
-                        int tbz, tz, tzlen;
-                        cross_target_z(cg, P.nz, bz, zlen, lz, cz, tbz, tz, tzlen);
-                        const int64_t t = ((int64_t)tbz * cg.yt + tby) * cg.xt + tbx;
-                        cross[t * tvals + cross_slot<i>(ttx, tty, tz, cg.zc, tzlen)] = v;
-                    }
-                });
+        // the staged lateral face-crossing values to the inbox of the tile
+        // they enter (entries of solid or bounce-back sources hold stale
+        // values; the fix-up reads only entries of fluid sources).  Entry
+        // pr of a face's direction pairs is decoded from bit-packed tables.
+        for (int k = threadIdx.x; k < XHALO + YRING; k += KNT) {
+            T v;
+            bool ok;
+            int cz, tbx, tby, slot_lo, slot_mul;   // slot = slot_lo + slot_mul * tz
+            if (k < XHALO) {
+                const int pr = k / KTY, ry = k % KTY;     // pair (side, direction), target row
+                const int i = (int)((FaceTab<0>::DIR >> (5 * pr)) & 31u);
+                const int cy = (int)((FaceTab<0>::CY >> (2 * pr)) & 3u) - 1;
+                cz = (int)((FaceTab<0>::CZ >> (2 * pr)) & 3u) - 1;
+                const bool east = pr >= 5;                // c_x = +1
+                ok = (unsigned)(ry - cy) < (unsigned)KTY; // a source row of this tile
+                v = xch[buf][i - 1][ry][east ? KHX - 1 : 0];
+                tbx = east ? (bx == cg.xt - 1 ? 0 : bx + 1) : (bx == 0 ? cg.xt - 1 : bx - 1);
+                tby = by;
+                // x-face slot ((side 5 + k) zc + tz) KTY + ly, side 0 for c_x = +1
+                slot_lo = (east ? pr - 5 : pr + 5) * cg.zc * KTY + ry;
+                slot_mul = KTY;
             } else {
-                const int q = k - XRING;
-                const int pr = q / KTX, sx = q % KTX;     // pair (side, direction), source x
-                static_for<0, 10>([&](auto pc) {
-                    constexpr int pp = decltype(pc)::value;
-                    constexpr int side = pp / 5, kk = pp % 5;
-                    constexpr int i = L::dir_with<1, side ? 1 : -1>(kk);
-                    constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-                    if (pr == pp && sx + cx >= 0 && sx + cx < KTX) {   // x-face crossings are in the x ring
-                        const int sy = cy > 0 ? KTY - 1 : 0;
-                        const int tty = sy + cy - (cy > 0 ? KTY : -KTY);
-                        const int tby = cy > 0 ? (by == cg.yt - 1 ? 0 : by + 1) : (by == 0 ? cg.yt - 1 : by - 1);
-                        int tbz, tz, tzlen;
-                        cross_target_z(cg, P.nz, bz, zlen, lz, cz, tbz, tz, tzlen);
-                        const int64_t t = ((int64_t)tbz * cg.yt + tby) * cg.xt + bx;
-                        cross[t * tvals + cross_slot<i>(sx + cx, tty, tz, cg.zc, tzlen)] = v;
-                    }
-                });
+                const int q = k - XHALO;
+                const int pr = q / KHX, hx = q % KHX;     // pair (side, direction), target x + 1
+                const int cx = (int)((FaceTab<1>::CX >> (2 * pr)) & 3u) - 1;
+                cz = (int)((FaceTab<1>::CZ >> (2 * pr)) & 3u) - 1;
+                const int kx = (int)((FaceTab<1>::KX >> (3 * pr)) & 7u);
+                const bool north = pr >= 5;               // c_y = +1
+                const int ttx = hx - 1;
+                ok = (unsigned)(ttx - cx) < (unsigned)KTX;  // a source column of this tile
+                v = ring[buf][q];
+                const int ly = north ? 0 : KTY - 1;
+                tby = north ? (by == cg.yt - 1 ? 0 : by + 1) : (by == 0 ? cg.yt - 1 : by - 1);
+                if (ttx < 0 || ttx >= KTX) {
+                    // also crosses an x face: filed under x in the diagonal tile
+                    const bool east = ttx >= KTX;
+                    tbx = east ? (bx == cg.xt - 1 ? 0 : bx + 1) : (bx == 0 ? cg.xt - 1 : bx - 1);
+                    slot_lo = ((east ? 0 : 5) + kx) * cg.zc * KTY + ly;
+                    slot_mul = KTY;
+                } else {
+                    // y-face slot 10 zc KTY + ((side 5 + k) zc + tz) KTX + lx, side 0 for c_y = +1
+                    tbx = bx;
+                    slot_lo = 10 * cg.zc * KTY + (north ? pr - 5 : pr + 5) * cg.zc * KTX + ttx;
+                    slot_mul = KTX;
+                }
+            }
+            if (ok) {
+                int tbz, tz, tzlen;
+                cross_target_z(cg, P.nz, bz, zlen, lz, cz, tbz, tz, tzlen);
+                const int64_t t = ((int64_t)tbz * cg.yt + tby) * cg.xt + tbx;
+                cross[t * tvals + slot_lo + slot_mul * tz] = v;
             }
         }
         T acc = T(0);
         if (fluid) {
             const uint32_t take = m | lat_in;   // bounce-back, or a source in the tile
             acc = b0;
+            // unconditional LDS reads, selected (slots not taken may hold
+            // stale values)
             static_for<1, 9>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
-                if ((take >> i) & 1u) acc += xch[buf][i - 1][ty][tx];
+                const T v = xch[buf][i - 1][ty][tx + 1];
+                acc += ((take >> i) & 1u) ? v : T(0);
             });
+            const uint32_t up = lz > 0 ? lat_in : 0u;
             static_for<9, 14>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
-                if ((m >> i) & 1u) acc += bbu[i - 9];
-                else if (((lat_in >> i) & 1u) && lz > 0) acc += upv[i - 9];
+                acc += ((m >> i) & 1u) ? bbu[i - 9] : (((up >> i) & 1u) ? upv[i - 9] : T(0));
             });
         }
         if (m_prev & 0x80000000u) {
@@ -1117,7 +1185,8 @@ __global__ __launch_bounds__(KNT, sizeof(T) == 8 ? 2 : 4) void k_collide_colour(
             T s = acc_prev;
             static_for<14, 19>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
-                if ((take >> i) & 1u) s += xch[buf][i - 1][ty][tx];
+                const T v = xch[buf][i - 1][ty][tx + 1];
+                s += ((take >> i) & 1u) ? v : T(0);
             });
             st(phi_out, x - plane, s);
         }
@@ -1131,7 +1200,7 @@ __global__ __launch_bounds__(KNT, sizeof(T) == 8 ? 2 : 4) void k_collide_colour(
         T s = acc_prev;
         static_for<14, 19>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
-            if ((m_prev >> i) & 1u) s += xch[buf][i - 1][ty][tx];
+            if ((m_prev >> i) & 1u) s += xch[buf][i - 1][ty][tx + 1];
         });
         st(phi_out, xy + plane * (uint32_t)(z1 - 1), s);
     }
