@@ -346,10 +346,16 @@ def main() -> int:
     main_run = hot_path(args, args.precision, form, layout)
     result = main_run.pop("line")
     if args.workload == "sphere" and args.precision == "f32" and not args.no_extra:
-        # the same box in 16-bit offset storage (same form), and the two-pass
-        # form in FP32, each timed like the headline run
-        r16 = hot_path(args, "f16ofs", form, layout)["line"]
+        # the same box in 16-bit offset storage, in both step forms (the
+        # faster is reported: with half the population bytes the
+        # collide-colour kernel's arithmetic outweighs the pass it saves),
+        # and the two-pass form in FP32, each timed like the headline run
+        forms16 = [form] + (["two-pass"] if form != "two-pass" else [])
+        r16s = [hot_path(args, "f16ofs", f, layout)["line"] for f in forms16]
+        r16 = min(r16s, key=lambda r: r["ms_per_step"])
         result["f16ofs"] = {"value": r16["value"], "unit": "MLUPS", "ms_per_step": r16["ms_per_step"],
+                            "form": r16["config"]["form"],
+                            "ms_per_step_by_form": {r["config"]["form"]: r["ms_per_step"] for r in r16s},
                             "speedup_over_f32": round(r16["value"] / result["value"], 3),
                             "roofline": r16["roofline"], "step_roofline": r16["step_roofline"],
                             "phase_ms_per_step": r16["phase_ms_per_step"], "mass_drift": r16["mass_drift"]}

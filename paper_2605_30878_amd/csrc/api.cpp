@@ -81,6 +81,12 @@ static void lattice_table(int lattice, int& D, int& Q, int& NC, const int (**c)[
     }
 }
 
+// Plane stride of the per-node fields: n rounded up to 128 (planes of 2-,
+// 4- and 8-byte values stay 256-byte aligned), plus 128 so that the planes
+// of a power-of-two box do not start at power-of-two distances (measured
+// on the 256^3 box: 1 to 2 % per step).
+static int64_t plane_stride(int64_t n) { return (n + 127) / 128 * 128 + 128; }
+
 // bytes of one stored population, and of every other per-node value
 static size_t elem_size(uint32_t prec) { return prec == LBM_FP64 ? 8 : (prec == LBM_FP32 ? 4 : 2); }
 static size_t phi_size(uint32_t prec) { return prec == LBM_FP64 ? 8 : 4; }
@@ -184,7 +190,7 @@ int lbm_create(const lbm_params* P, lbm_ctx** out) {
     const double* w;
     lattice_table((int)P->lattice, c->D, c->Q, c->NC, &cv, &w);
     c->n = n;
-    c->S = (n + 127) / 128 * 128;   // plane stride: planes of 2-, 4- and 8-byte values stay 256-byte aligned
+    c->S = plane_stride(n);
     // The kernels address a field plane with 32-bit byte offsets.
     if ((uint64_t)c->S * std::max(elem_size(P->precision), phi_size(P->precision)) > 0xFFFFFFFFull) {
         delete c;
@@ -504,7 +510,7 @@ int lbm_set_geometry(lbm_ctx* c, const lbm_solid* solids, int32_t count) {
             }
         }
         c->M = M;
-        c->S = (M + 127) / 128 * 128;
+        c->S = plane_stride(M);
         c->sp.n = M;
         c->sp.S = c->S;
     }

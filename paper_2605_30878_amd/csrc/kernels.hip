@@ -216,6 +216,19 @@ __device__ __forceinline__ void grad_stencil(const T (&ph)[L::Q], T& gx, T& gy, 
     gz *= T(3);
 }
 
+// 1/x and 1/sqrt(x): FP64 divides; FP32 takes the hardware reciprocal and
+// reciprocal square root (1 ulp), a tenth of a divide's instructions.
+template <class T>
+__device__ __forceinline__ T recip(T x) {
+    if constexpr (std::is_same<T, float>::value) return __builtin_amdgcn_rcpf(x);
+    else return T(1) / x;
+}
+template <class T>
+__device__ __forceinline__ T rsqrt_(T x) {
+    if constexpr (std::is_same<T, float>::value) return __builtin_amdgcn_rsqf(x);
+    else return T(1) / sqrt(x);
+}
+
 // Recolouring vector of Eq. A12, G = (2/W) max(phi (1 - phi), 0) n_phi:
 // the normal where |grad phi| is resolved, the amplitude clamped at 0 where
 // phi leaves [0, 1].
@@ -226,7 +239,7 @@ __device__ __forceinline__ void recolour_vector(T phi, T gx, T gy, T gz, T inv_W
     amp = amp > T(0) ? amp : T(0);
     G[0] = G[1] = G[2] = T(0);
     if (gn2 > n_thresh2) {
-        const T k = T(2) * inv_W * amp / sqrt(gn2);
+        const T k = T(2) * inv_W * amp * rsqrt_(gn2);
         G[0] = k * gx;
         G[1] = k * gy;
         G[2] = k * gz;
@@ -276,7 +289,7 @@ __device__ __forceinline__ void macro_stage(const T (&N)[L::Q], const T (&ph)[L:
     const T rho = P.rho_g + P.drho * phi;
     const T inv_nu = P.inv_nu_g + P.dinv_nu * phi;
     // tau = 1/2 + nu / cs^2 = 1/2 + 3 / inv_nu; only 1/tau is used, one division
-    const T inv_tau = inv_nu / (T(0.5) * inv_nu + T(3));
+    const T inv_tau = inv_nu * recip(T(0.5) * inv_nu + T(3));
     m.rho = rho;
     m.inv_tau = inv_tau;
     // Moments of N over opposite pairs: a = n_i + n_opp carries the even
@@ -333,7 +346,7 @@ __device__ __forceinline__ void macro_stage(const T (&N)[L::Q], const T (&ph)[L:
     T Fy = mu * gy - p * gry + kv * (dxy * grx + dyy * gry + dyz * grz) + rho * P.g[1];
     T Fz = mu * gz - p * grz + kv * (dxz * grx + dyz * gry + dzz * grz) + rho * P.g[2];
     if constexpr (L::D == 2) Fz = 0;
-    const T inv_rho = T(1) / rho;
+    const T inv_rho = recip(rho);
     m.a[0] = Fx * inv_rho;
     m.a[1] = Fy * inv_rho;
     m.a[2] = Fz * inv_rho;
@@ -488,7 +501,11 @@ __device__ __forceinline__ T compact_term(T n, T phi_src, T gx, T gy, T gz, T p,
     if constexpr (cz != 0) cG += cmul<cz>(gz);
     const T sG = sgn * cG;
     const T chi = L::w[I] == L::w[1] ? P.chi_a : P.chi_d;   // equals P.chi[I] (one value per weight class)
-    return (phi_src + sG) * chi + phi_src * n + sG * (wi * T(3) * p);
+    // phi (chi_i + n) + sG (chi_i + 3 w_i p): at one source node phi chi_i
+    // and chi_i + 3 w_i p take one value per weight class
+    const T pc = phi_src * chi;
+    const T k = wi * T(3) * p + chi;
+    return (phi_src * n + pc) + sG * k;
 }
 
 // Post-stream liquid population B_i(y) from the compact record.  nb[i] is
