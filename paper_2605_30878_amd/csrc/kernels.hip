@@ -418,22 +418,30 @@ __device__ __forceinline__ void collide_stage(const Macro<T>& m, const T (&Pi)[6
 }
 
 // Neighbour index tables of a node: nb[i] = index of x + c_i (periodic).
+// The node index plus wrap-aware offsets along each axis, summed per
+// direction (the same indices as wrapping each coordinate).
 template <class L, class I>
 __device__ __forceinline__ void neighbours(int ix, int iy, int iz, int nx, int ny, int nz, I (&nb)[L::Q]) {
-    const int xm = ix == 0 ? nx - 1 : ix - 1, xp = ix == nx - 1 ? 0 : ix + 1;
-    const int ym = iy == 0 ? ny - 1 : iy - 1, yp = iy == ny - 1 ? 0 : iy + 1;
-    int zm = 0, zp = 0;
+    const I x = (I)ix + (I)nx * ((I)iy + (I)ny * (I)iz);
+    const I plane = (I)nx * (I)ny;
+    const I oxp = ix == nx - 1 ? (I)0 - (I)(nx - 1) : (I)1, oxm = ix == 0 ? (I)(nx - 1) : (I)0 - (I)1;
+    const I oyp = iy == ny - 1 ? (I)0 - (I)(ny - 1) * (I)nx : (I)nx, oym = iy == 0 ? (I)(ny - 1) * (I)nx : (I)0 - (I)nx;
+    I ozp = 0, ozm = 0;
     if constexpr (L::D == 3) {
-        zm = iz == 0 ? nz - 1 : iz - 1;
-        zp = iz == nz - 1 ? 0 : iz + 1;
+        ozp = iz == nz - 1 ? (I)0 - (I)(nz - 1) * plane : plane;
+        ozm = iz == 0 ? (I)(nz - 1) * plane : (I)0 - plane;
     }
     static_for<0, L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
-        const int X = cx == 0 ? ix : (cx > 0 ? xp : xm);
-        const int Y = cy == 0 ? iy : (cy > 0 ? yp : ym);
-        const int Z = cz == 0 ? iz : (cz > 0 ? zp : zm);
-        nb[i] = (I)X + (I)nx * ((I)Y + (I)ny * (I)Z);
+        I o = 0;
+        if constexpr (cx > 0) o += oxp;
+        if constexpr (cx < 0) o += oxm;
+        if constexpr (cy > 0) o += oyp;
+        if constexpr (cy < 0) o += oym;
+        if constexpr (cz > 0) o += ozp;
+        if constexpr (cz < 0) o += ozm;
+        nb[i] = x + o;
     });
 }
 
@@ -833,8 +841,6 @@ __device__ __forceinline__ void collide_core(const SN* __restrict__ Nsrc, SN* __
     for (int a = 0; a < L::D; a++) st(Gdst + (int64_t)a * S, x, G[a]);
     st(Gdst + (int64_t)GRec<L>::P * S, x, m.p);
 }
-
-// The same for the node at (ix, iy, iz) of the box layout.
 template <class L, class T, class SN, bool NT = true>
 __device__ __forceinline__ void collide_node(const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
                                              T* __restrict__ Gdst, const T* __restrict__ phi,
@@ -1087,46 +1093,52 @@ __global__ __launch_bounds__(KNT, sizeof(T) == 8 ? 2 : 4) void k_collide_colour(
             e[0] = NS::enc_off(closure);
             st(Ndst, x, e[0]);   // the rest population stays at x
             b0 = mc.phi * (P.chi[0] + NS::dec(e[0], P.n_s));
+            // every direction streams to x + c_i; where that node is solid
+            // the value lands in an entry that nothing reads (a solid node's
+            // N, its hand-over slot, an inbox slot the fix-up skips), and the
+            // bounce-back pass below delivers it
             static_for<1, Q>([&](auto ic) {
                 constexpr int i = decltype(ic)::value;
-                constexpr int j = L::opp[i];
                 constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
                 const T b = compact_term<L, T, i>(NS::dec(e[i], P.n_s), mc.phi, G[0], G[1], G[2], mc.p, T(1), P);
-                // a bounce-back link returns N*_i and B*_i to x in direction
-                // j = opp(i); B*_i then takes x's own slot of direction j (its
-                // source is solid, so nothing else is handed to that slot),
-                // in the other buffer when c_z(j) != 0: read with the plane
-                // above (c_z = -1) or by this plane's read of the previous
-                // buffer (c_z = +1)
-                const bool bb = (bbm >> i) & 1u;
-                m |= bb ? (1u << j) : 0u;
-                st(Ndst, bb ? (uint32_t)j * S32 + x : (uint32_t)i * S32 + nbr(ic), e[i]);
-                const int own = hx(L::c[j][2] == 0 ? buf : buf ^ 1, j - 1, ty, tx + 1);
+                st(Ndst, (uint32_t)i * S32 + nbr(ic), e[i]);
                 // the branches on ty and lz are wave-uniform
                 const bool y_out = cy != 0 && (ty + cy < 0 || ty + cy >= KTY);
                 const bool z_out = cz != 0 && (lz + cz < 0 || lz + cz >= zlen);
-                if (z_out && !y_out) {
+                if (y_out) {
+                    // leaves through a y face (the whole wave of an edge row): the y ring
+                    if constexpr (cy != 0) sm[rg(buf, ((cy > 0 ? 5 : 0) + cross_k<i, 1, cy>()) * KHX + tx + cx + 1)] = b;
+                } else if (z_out && (cx == 0 || (unsigned)(tx + cx) < (unsigned)KTX)) {
                     // the chunk's bottom or top plane: a target in this tile's
                     // column lies in the neighbouring chunk (inbox)
-                    if (!bb && (cx == 0 || (unsigned)(tx + cx) < (unsigned)KTX)) {
-                        int tbz, tz, tzlen;
-                        cross_target_z(cg, P.nz, bz, zlen, lz, cz, tbz, tz, tzlen);
-                        const int64_t t = ((int64_t)tbz * cg.yt + by) * cg.xt + bx;
-                        cross[t * tvals + cross_slot<i>(tx + cx, ty + cy, tz, cg.zc, tzlen)] = b;
-                    } else {
-                        sm[bb ? own : hx(buf, i - 1, ty, tx + cx + 1)] = b;   // own slot, or halo column
-                    }
+                    int tbz, tz, tzlen;
+                    cross_target_z(cg, P.nz, bz, zlen, lz, cz, tbz, tz, tzlen);
+                    const int64_t t = ((int64_t)tbz * cg.yt + by) * cg.xt + bx;
+                    cross[t * tvals + cross_slot<i>(tx + cx, ty + cy, tz, cg.zc, tzlen)] = b;
                 } else {
-                    // in the tile or a halo column; through a y face: the y ring
-                    int nrm;
-                    if constexpr (cy != 0)
-                        nrm = y_out ? rg(buf, ((cy > 0 ? 5 : 0) + cross_k<i, 1, cy>()) * KHX + tx + cx + 1)
-                                    : hx(buf, i - 1, ty + cy, tx + cx + 1);
-                    else
-                        nrm = hx(buf, i - 1, ty, tx + cx + 1);
-                    sm[bb ? own : nrm] = b;
+                    // in the tile, or a halo column
+                    sm[hx(buf, i - 1, ty + cy, tx + cx + 1)] = b;
                 }
             });
+            if (bbm) {
+                // bounce-back links (nodes next to a solid): N*_i and B*_i
+                // return to x in direction j = opp(i); B*_i takes x's own slot
+                // of direction j (its source is solid, so nothing else is
+                // handed to it), in the other buffer when c_z(j) != 0: read
+                // with the plane above (c_z = -1) or by this plane's read of
+                // the previous buffer (c_z = +1)
+                static_for<1, Q>([&](auto ic) {
+                    constexpr int i = decltype(ic)::value;
+                    constexpr int j = L::opp[i];
+                    if ((bbm >> i) & 1u) {
+                        const T b =
+                            compact_term<L, T, i>(NS::dec(e[i], P.n_s), mc.phi, G[0], G[1], G[2], mc.p, T(1), P);
+                        st(Ndst, (uint32_t)j * S32 + x, e[i]);
+                        sm[hx(L::c[j][2] == 0 ? buf : buf ^ 1, j - 1, ty, tx + 1)] = b;
+                        m |= 1u << j;
+                    }
+                });
+            }
         }
         if (!fluid) {
             // a solid source sends nothing: its off-tile slots get zeros so
