@@ -143,10 +143,12 @@ def hbm_ceiling(gib: int = 4, repeats: int = 10) -> dict:
     return out
 
 
-def inbox_values(shape, zc_blocks: int = 2048) -> int:
+def inbox_values(shape, zc_blocks: int = 6144) -> int:
     """Values the collide-colour step writes to its inbox per launch: for
     each 64 x 8 x zc tile-chunk, the (node, direction) pairs whose source
-    lies outside it, counted over the box geometry (solids included)."""
+    lies outside it, counted over the box geometry (solids included).  The
+    chunk length follows the library's choice (about zc_blocks workgroups
+    per launch, at least 4 planes)."""
     nx, ny, nz = shape
     KTX, KTY = 64, 8
     xt, yt = nx // KTX, ny // KTY
