@@ -86,7 +86,32 @@ CPU_WINDOWS = {
     "d2q9_cylinder_128": (lambda W: W.cylinder_d2q9_128(), 2000),
     "d3q19_sphere_64": (lambda W: W.sphere_d3q19(64, precision=W.FP64), 200),
     "d3q19_sphere_256": (lambda W: W.sphere_d3q19(256, precision=W.FP64), 3),
+    "d3q19_sphere_256_1": (lambda W: W.sphere_d3q19(256, precision=W.FP64), 1),
 }
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (Linux), or the platform's processor string."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+
+    return platform.processor() or "unknown"
+
+
+def single_thread_window(name: str) -> dict:
+    """One oracle window in a child process with one OpenMP thread."""
+    import subprocess
+
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    res = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-window", name],
+                         env=env, capture_output=True, text=True, check=True)
+    return json.loads(res.stdout.strip().splitlines()[-1])
 
 
 def cpu_window(name: str) -> dict:
@@ -108,6 +133,8 @@ def cpu_windows(threads) -> list:
 
     out = []
     for name in CPU_WINDOWS:
+        if name.endswith("_1"):   # the single-thread sample of cpu_baseline
+            continue
         for t in threads:
             env = dict(os.environ, OMP_NUM_THREADS=str(t))
             res = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-window", name],
@@ -286,7 +313,7 @@ def main() -> int:
                          "porosity 0.40, theta 45, body force 1e-6")
     ap.add_argument("--theta", type=float, default=90.0)
     ap.add_argument("--precision", choices=["f32", "f64", "f16ofs", "bf16ofs"], default="f32")
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=12)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve", choices=["full", "reduced", "none"], default="full",
                     help="served mix: full = FP16 storage at the stated size (256 requests, full steps) plus a "
@@ -407,8 +434,15 @@ def main() -> int:
                             f"{len(sample.solids)} spheres; FP64 oracle, OpenMP over nodes), after 1 untimed step")
             result["cpu_baseline"] = cb
         else:
-            result["cpu_baseline"] = cpu_baseline(W.sphere_d3q19(args.size, theta=args.theta, precision=W.FP64),
-                                                  args.cpu_steps)
+            cb = cpu_baseline(W.sphere_d3q19(args.size, theta=args.theta, precision=W.FP64), args.cpu_steps)
+            cb["cpu_model"] = cpu_model()
+            if args.size == 256:
+                # the same box on one core: one step in a child process
+                st = single_thread_window("d3q19_sphere_256_1")
+                cb["single_thread"] = {"value": st["value"], "unit": "MLUPS", "cores": 1,
+                                       "sample": "1 step of the same box (FP64 oracle, one OpenMP thread), "
+                                                 "after 1 untimed step"}
+            result["cpu_baseline"] = cb
     print(json.dumps(result), flush=True)
     return 0
 

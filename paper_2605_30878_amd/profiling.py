@@ -6,6 +6,7 @@ plain device copy of known size.
     python -m paper_2605_30878_amd.profiling stats <kernel_stats.csv> <out.md> "<command>"
     python -m paper_2605_30878_amd.profiling traffic <fetch.csv> <write.csv> <copy_fetch.csv> \
         <copy_write.csv> <copy_bytes> <workload_key> <out.md> "<commands>"
+    python -m paper_2605_30878_amd.profiling counters <out.md> "<commands>" <pass.csv> [<pass.csv> ...]
 """
 from __future__ import annotations
 
@@ -73,6 +74,7 @@ def _itanium_short(base: str) -> str:
 
 
 def short_name(name: str) -> str:
+    name = name.replace("(anonymous namespace)::", "")
     base = name.split("(")[0]
     if base.startswith("void "):
         base = base[5:]
@@ -114,6 +116,43 @@ def traffic(fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_bytes: fl
     return out, f_scale, w_scale
 
 
+COUNTER_KERNELS = ("k_colour_tile", "k_collide_stream", "k_collide_colour", "k_colour_fixup", "k_ghost")
+PER_WAVE = ("SQ_INSTS_VALU", "SQ_INSTS_SALU", "SQ_INSTS_LDS", "SQ_INSTS_VMEM_RD", "SQ_INSTS_VMEM_WR")
+OF_WAVE_CYCLES = ("SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_SCA", "SQ_ACTIVE_INST_LDS", "SQ_ACTIVE_INST_ANY",
+                  "SQ_WAIT_INST_ANY", "SQ_WAIT_ANY")
+
+
+def counters_markdown(paths, command: str) -> str:
+    """SQ / TA / TCC counters of the step kernels, averaged over dispatches
+    (several single-pass runs of the same program): instructions per wave,
+    activity and waits as a share of SQ_WAVE_CYCLES, and the raw means."""
+    acc = defaultdict(lambda: defaultdict(list))
+    for path in paths:
+        for r in csv.DictReader(open(path)):
+            name = short_name(r["Kernel_Name"])
+            if any(k in name for k in COUNTER_KERNELS):
+                acc[name][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    lines = ["Commands:", "", "```", command, "```", "",
+             "Instructions per wave; activity and waits as a share of SQ_WAVE_CYCLES "
+             "(the sum over waves of their resident cycles).", ""]
+    for name in sorted(acc):
+        d = {c: sum(v) / len(v) for c, v in acc[name].items()}
+        waves = d.get("SQ_WAVES", 0.0)
+        lines.append(f"### `{name}`")
+        lines.append("")
+        lines.append("| counter | mean per dispatch | derived |")
+        lines.append("|---|---|---|")
+        for c in sorted(d):
+            derived = ""
+            if c in PER_WAVE and waves:
+                derived = f"{d[c] / waves:.1f} per wave"
+            elif c in OF_WAVE_CYCLES and d.get("SQ_WAVE_CYCLES"):
+                derived = f"{100.0 * d[c] / d['SQ_WAVE_CYCLES']:.1f} % of wave-cycles"
+            lines.append(f"| {c} | {d[c]:.4g} | {derived} |")
+        lines.append("")
+    return "\n".join(lines)
+
+
 def main(argv):
     if argv[0] == "stats":
         md = stats_markdown(argv[1], argv[3])
@@ -144,6 +183,11 @@ def main(argv):
                          f"{v['hbm_bytes_per_launch'] / 1e6:.1f} |")
         with open(out_md, "w") as f:
             f.write("\n".join(lines) + "\n")
+        return 0
+    if argv[0] == "counters":
+        md = counters_markdown(argv[3:], argv[2])
+        with open(argv[1], "w") as f:
+            f.write(md)
         return 0
     raise SystemExit(__doc__)
 

@@ -12,6 +12,7 @@ import oracle
 from paper_2605_30878_amd import measure
 from paper_2605_30878_amd import workloads as W
 
+import analytic
 from analytic import drop_on_solid
 
 
@@ -158,35 +159,9 @@ def _layered_channel(lattice, rho_l, mu_l, ny=34, g=1e-6, steps=40000, visc=0):
     return wl, u, phi
 
 
-def _steady_layered(wl, phi, g):
-    """Steady 1D solution of d/dy (mu du/dy) = -rho g with u = 0 on both walls
-    (the x-momentum balance of Eq. 1 with the stress of its text), mu = rho nu
-    from the run's own phi (linear between nodes): rho = rho_l phi + rho_g
-    (1 - phi) and harmonic 1/nu = phi/nu_l + (1 - phi)/nu_g (text after
-    Eq. 3).  Integrated on a fine grid by the trapezoid rule."""
-    ny = phi.size
-    yk = np.arange(1, ny - 1, dtype=float)
-    y = np.linspace(0.5, ny - 1.5, 100001)
-    f = np.interp(y, yk, phi[1:ny - 1])
-    rho = wl.rho_g + (wl.rho_l - wl.rho_g) * f
-    nu = 1.0 / (f / (wl.mu_l / wl.rho_l) + (1.0 - f) / (wl.mu_g / wl.rho_g))
-    mu = rho * nu
-    dy = y[1] - y[0]
-
-    def cumint(v):
-        out = np.zeros_like(v)
-        out[1:] = np.cumsum(0.5 * (v[1:] + v[:-1])) * dy
-        return out
-
-    shear = g * cumint(rho)             # integral of rho g from the bottom wall
-    a, b = cumint(1.0 / mu), cumint(shear / mu)
-    u = (b[-1] / a[-1]) * a - b         # mu du/dy = C - shear, u(0.5) = u(ny - 3/2) = 0
-    return np.interp(yk, y, u)
-
-
 def _layered_error(lattice, rho_l, mu_l, visc=0):
     wl, u, phi = _layered_channel(lattice, rho_l, mu_l, visc=visc)
-    want = _steady_layered(wl, phi, 1e-6)
+    want = analytic.steady_layered(wl, phi, 1e-6)
     return float(np.max(np.abs(u[1:-1] - want)) / np.max(np.abs(want)))
 
 
