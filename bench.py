@@ -287,7 +287,12 @@ def hot_path(args, precision: str, form: str, layout: str) -> dict:
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel": kernel, "alg_bytes_per_launch": alg_bytes,
-                     "avg_launch_ms": round(k_ms, 5)},
+                     "avg_launch_ms": round(k_ms, 5)} | ({"note": (
+                         "the collide-colour kernel also forms the next colour field, so a step moves "
+                         f"{impl_bytes:.0f} B per update against the two-pass form's "
+                         f"{(Q * s_n + 2 * s_t + (D + 1) * s_t) + (2 * Q * s_n + s_t + (D + 1) * s_t)} B; its time is "
+                         "set by instruction issue and a per-plane barrier at two workgroups per CU, not by HBM")}
+                         if fused else {}),
         "step_roofline": {"bytes_per_update": step_bytes, "impl_bytes_per_update": round(impl_bytes, 2),
                           "roofline_mlups": round(HBM_PEAK_GBS * 1e9 / step_bytes / 1e6, 1),
                           "frac": round(mlups / (HBM_PEAK_GBS * 1e9 / step_bytes / 1e6), 4),

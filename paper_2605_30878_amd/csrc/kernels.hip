@@ -26,8 +26,8 @@
 // Populations are SoA planes [Q][S], double-buffered; phi is double-buffered
 // so that the ghost update reads last step's solid values while writing the
 // new ones, and the previous step's phi at fluid nodes stays available for
-// the compact B.  Every kernel is HBM-bound; nothing is a dense contraction,
-// so no MFMA is used.
+// the compact B.  Nothing is a dense contraction, so no MFMA is used; HBM
+// bandwidth is the roofline.
 //
 // Launch forms of the colour and collide kernels (one set of per-node
 // functions, so every form computes the same values bit for bit):
@@ -35,10 +35,12 @@
 //     compact record of three planes and a one-node ring in LDS) and the
 //     row kernel k_collide_stream;
 //   box planes otherwise: the row kernels k_colour_compact, k_collide_stream;
-//   fluid-node list over box planes: k_colour_list, k_collide_list;
 //   fluid-only slots (packings): k_colour_sparse, k_collide_sparse;
 //   many runs at once: kb_colour, kb_ghost, kb_collide over a job table;
-//   fused one-launch D3Q19 step (opt-in): k_ghost_direct, k_step_fused.
+//   the collide-colour step (LBM_OPT_FUSED, D3Q19 boxes tiled by 64 x 8):
+//     k_ghost, then k_collide_colour, which also forms the next step's phi
+//     from the populations it streams (an LDS hand-over inside 64 x 8 tile
+//     columns, an HBM inbox across their faces), then k_colour_fixup.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
