@@ -100,27 +100,63 @@ def test_sphere_d3q19_fp64_parity_tiled_colour(case):
     _run_pair(wl, [1, 2, 25, 200], TOL64)
 
 
-@pytest.mark.parametrize("case", ["one_column", "several_columns"])
+def _cc_sphere(shape, sc, rs, lc, rl, theta):
+    return W.Workload(name="d3q19_cc", lattice=W.D3Q19, shape=shape, rho_l=1000.0, rho_g=1.0, mu_l=10.0,
+                      mu_g=0.1, sigma=0.01, W=4.0, theta=theta, solids=[W.Solid(0, sc, rs)],
+                      liquid=[W.LiquidRegion("ball", lc, rl, width=4.0)])
+
+
+def _cc_channel(shape, lc, rl, theta):
+    """A drop on the lower of two flat walls (solid rows y = 0 and y = ny - 1)."""
+    return W.Workload(name="d3q19_cc_wall", lattice=W.D3Q19, shape=shape, rho_l=1000.0, rho_g=1.0, mu_l=10.0,
+                      mu_g=0.1, sigma=0.01, W=4.0, theta=theta,
+                      solids=[W.Solid(1, (0.0, 0.5, 0.0), normal=(0.0, 1.0, 0.0)),
+                              W.Solid(1, (0.0, shape[1] - 1.5, 0.0), normal=(0.0, -1.0, 0.0))],
+                      liquid=[W.LiquidRegion("ball", lc, rl, width=4.0)])
+
+
+# collide-colour parity boxes: (workload, compared steps).  Boxes thinner
+# than a ball's diameter take a drop on a flat wall; those are compared up
+# to step 25, while a 1e-15 perturbation of the oracle's initial field
+# stays below 1e-14 (by step 200 it grows: see below).
+CC_BOXES = {
+    # one tile column across x, a short last z-chunk
+    "one_column": (lambda: _cc_sphere((64, 32, 22), (30.0, 15.0, 6.0), 6.0, (30.0, 15.0, 12.5), 5.5, 120.0),
+                   [1, 2, 25, 200]),
+    # two tile columns each way
+    "several_columns": (lambda: _cc_sphere((128, 16, 18), (62.0, 7.0, 4.0), 5.0, (62.0, 7.0, 9.5), 4.5, 120.0),
+                        [1, 2, 25, 200]),
+    # one 64 x 8 tile: its own x and y neighbour; z-chunks of 4, 4 and 1 planes
+    "own_neighbour_tile": (lambda: _cc_sphere((64, 8, 9), (30.0, 3.5, 2.0), 2.5, (30.0, 3.5, 5.5), 2.5, 60.0),
+                           [1, 2, 25, 200]),
+    # a last z-chunk of one plane
+    "one_plane_last_chunk": (lambda: _cc_channel((64, 16, 5), (30.0, 3.0, 2.0), 4.0, 120.0), [1, 2, 25]),
+    # boxes thinner than a chunk: one chunk of 3, 2 or 1 planes, whose c_z
+    # crossings wrap to itself
+    "three_planes": (lambda: _cc_channel((64, 16, 3), (30.0, 3.0, 1.0), 4.0, 90.0), [1, 2, 25]),
+    "two_planes": (lambda: _cc_channel((64, 16, 2), (30.0, 3.0, 0.5), 4.0, 120.0), [1, 2, 25]),
+    "one_plane": (lambda: _cc_channel((64, 16, 1), (30.0, 3.0, 0.0), 4.0, 60.0), [1, 2, 25]),
+}
+
+
+@pytest.mark.parametrize("case", list(CC_BOXES))
 def test_sphere_d3q19_fp64_parity_collide_colour(case):
     """Boxes stepped in the collide-colour form (LBM_OPT_FUSED: the collide
     kernel also forms the next step's colour field; values crossing a
     64 x 8 column or z-chunk face go through the inbox and the fix-up),
-    density ratio 1000: 64 x 32 x 22 (one column across x, a short last
-    z-chunk) and 128 x 16 x 18 (two columns each way).  The runs keep no
-    liquid populations, so N, phi, u and p are compared.  Both boxes are
-    well conditioned: a 1e-15 perturbation of the oracle's initial field
-    stays below 3e-15 in phi over 200 steps (with the drop 0.5 nodes lower
-    in the first box it grew to 6e-14: the interface normal switches off
-    below |grad phi| = 1e-12 (reading R-n), so phi of order 1e-12 far from
-    the drop is not a smooth function of the state)."""
-    if case == "one_column":
-        shape, sc, rs, lc, rl = (64, 32, 22), (30.0, 15.0, 6.0), 6.0, (30.0, 15.0, 12.5), 5.5
-    else:
-        shape, sc, rs, lc, rl = (128, 16, 18), (62.0, 7.0, 4.0), 5.0, (62.0, 7.0, 9.5), 4.5
-    wl = W.Workload(name="d3q19_cc", lattice=W.D3Q19, shape=shape, rho_l=1000.0, rho_g=1.0,
-                    mu_l=10.0, mu_g=0.1, sigma=0.01, W=4.0, theta=120.0,
-                    solids=[W.Solid(0, sc, rs)], liquid=[W.LiquidRegion("ball", lc, rl, width=4.0)])
-    _run_pair(wl, [1, 2, 25, 200], TOL64, keys=("N", "phi", "u", "p"), options=1)
+    density ratio 1000, including the degenerate tilings (a tile that is its
+    own neighbour, one-plane chunks, boxes thinner than a chunk).  The runs
+    keep no liquid populations, so N, phi, u and p are compared.  Every box
+    is well conditioned over the compared steps: a 1e-15 perturbation of
+    the oracle's initial field stays below 3e-15 in phi over 200 steps in
+    the sphere boxes and below 1e-14 over 50 steps in the wall boxes (the
+    interface normal switches off below |grad phi| = 1e-12 (reading R-n), so
+    phi of order 1e-12 far from the drop is not a smooth function of the
+    state, and some boxes amplify such differences later: with the first
+    box's drop 0.5 nodes lower, 6e-14 by step 200)."""
+    make, steps = CC_BOXES[case]
+    wl = make()
+    _run_pair(wl, steps, TOL64, keys=("N", "phi", "u", "p"), options=1)
 
 
 @pytest.mark.parametrize("prec", [W.FP32, W.FP16_OFS], ids=["f32", "fp16ofs"])
