@@ -272,3 +272,28 @@ def test_set_geometry_rejects_bad_solids():
     assert lib.lbm_set_geometry(h, lbm.make_solids(wl.solids), len(wl.solids)) == lbm.OK
     assert lib.lbm_device_bytes(h, C.byref(nbytes)) == lbm.OK
     assert lib.lbm_destroy(h) == lbm.OK
+
+
+def test_collide_colour_inbox_only_when_the_form_applies():
+    """The collide-colour form (LBM_OPT_FUSED) addresses the Q population
+    planes from one base with 32-bit offsets, so it steps only boxes tiled by
+    64 x 8 whose populations take at most 4 GiB; its inbox is allocated only
+    then (other boxes step in the two-pass form)."""
+    lib = lbm.load_library()
+
+    def nbytes(shape, options):
+        wl = W.Workload(name="box", lattice=W.D3Q19, shape=shape, precision=W.FP32, theta=90.0, solids=[])
+        rc, h = _create(wl, options=options)
+        assert rc == lbm.OK
+        assert lib.lbm_set_geometry(h, lbm.make_solids([]), 0) == lbm.OK
+        out = C.c_size_t()
+        assert lib.lbm_device_bytes(h, C.byref(out)) == lbm.OK
+        lib.lbm_destroy(h)
+        return out.value
+
+    # 512 x 512 x 128 FP32: 19 planes of 128 MiB, 2.4 GiB: the form applies
+    assert nbytes((512, 512, 128), lbm.OPT_FUSED) > nbytes((512, 512, 128), 0)
+    # 512 x 512 x 256: 4.75 GiB of populations: stepped in the two-pass form
+    assert nbytes((512, 512, 256), lbm.OPT_FUSED) == nbytes((512, 512, 256), 0)
+    # a box not tiled by 64 x 8
+    assert nbytes((96, 64, 32), lbm.OPT_FUSED) == nbytes((96, 64, 32), 0)
