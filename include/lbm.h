@@ -113,8 +113,12 @@ enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_OFS = 2, LBM_BF16_OFS = 3 };
  * order, then one slot that stands for every other solid node.  A table of
  * Q - 1 slot indices per fluid node (4 (Q - 1) bytes) gives each fluid
  * node's neighbours.  Launches cover the fluid slots only, and a step
- * computes the same values as the box layout, bit for bit.  Fields still
- * cross the ABI in box order.  Restrictions: it excludes LBM_OPT_FUSED
+ * computes the same values as the box layout, bit for bit.  Streaming is
+ * pull: the device keeps each node's post-collision populations in its own
+ * slots and the next step gathers them (Eq. A16-A17 applied on read).
+ * Fields still cross the ABI in box order, and LBM_FIELD_N / _N_OFFSET
+ * still mean the post-stream populations (gathered on read, scattered on
+ * set).  Restrictions: it excludes LBM_OPT_FUSED
  * (lbm_create returns LBM_EINVAL); such contexts step
  * only through lbm_step (lbm_batch_step returns LBM_EINVAL); setting
  * LBM_FIELD_SOLID_PHI needs one value for all non-ghost solid nodes

@@ -35,7 +35,10 @@
 //     compact record of three planes and a one-node ring in LDS) and the
 //     row kernel k_collide_stream;
 //   box planes otherwise: the row kernels k_colour_compact, k_collide_stream;
-//   fluid-only slots (packings): k_colour_sparse, k_collide_sparse;
+//   fluid-only slots (packings): k_colour_sparse, k_collide_sparse, with
+//     pull streaming: N holds post-collision populations at their source
+//     slot, every reader gathers the post-stream N_i(y) through the
+//     neighbour table, and the collide kernel's stores are contiguous;
 //   many runs at once: kb_colour, kb_ghost, kb_collide over a job table;
 //   the collide-colour step (LBM_OPT_FUSED, D3Q19 boxes tiled by 64 x 8):
 //     k_ghost, then k_collide_colour, which also forms the next step's phi
@@ -520,24 +523,34 @@ __device__ __forceinline__ T compact_term(T n, T phi_src, T gx, T gy, T gz, T p,
 
 // Post-stream liquid population B_i(y) from the compact record.  nb[i] is
 // y + c_i, so the source y - c_i is nb[opp(i)]; at a bounce-back link the
-// source is y with c_i reversed.
-template <class L, class T, class SN, int I>
+// source is y with c_i reversed.  PULL: N holds post-collision populations
+// at their source node (fluid-only layout), so the post-stream N_i(y) is
+// read at the same source as the record: slot i of y - c_i, or slot opp(i)
+// of y at a bounce-back link.
+template <class L, class T, class SN, int I, bool PULL = false>
 __device__ __forceinline__ T compact_B(const SN* __restrict__ N, const T* __restrict__ phi_prev,
                                        const T* __restrict__ G, const uint8_t* __restrict__ flags,
                                        const KParams<T, L::Q>& P, uint32_t y, const uint32_t (&nb)[L::Q],
                                        bool near_solid) {
     const int64_t S = P.S;
-    const T n = NStore<T, SN>::dec(ld(N + (int64_t)I * S, y), P.n_s);
     if constexpr (I == 0) {
+        const T n = NStore<T, SN>::dec(ld(N, y), P.n_s);
         return ld(phi_prev, y) * (P.chi[0] + n);
     } else {
         constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
         uint32_t src = nb[L::opp[I]];
         T sgn = T(1);
+        bool bounce = false;
         if (near_solid && (ld(flags, src) & FLAG_SOLID)) {
             src = y;
             sgn = T(-1);
+            bounce = true;
         }
+        T n;
+        if constexpr (PULL)
+            n = NStore<T, SN>::dec(bounce ? ld(N + (int64_t)L::opp[I] * S, y) : ld(N + (int64_t)I * S, src), P.n_s);
+        else
+            n = NStore<T, SN>::dec(ld(N + (int64_t)I * S, y), P.n_s);
         const T gx = cx != 0 ? ld(G, src) : T(0);
         const T gy = cy != 0 ? ld(G + S, src) : T(0);
         const T gz = cz != 0 ? ld(G + 2 * S, src) : T(0);
@@ -567,7 +580,7 @@ __global__ __launch_bounds__(256) void k_colour_planes(const T* __restrict__ B, 
 
 // phi = sum_i B_i (i ascending) with B_i formed from the compact record, one
 // fluid node x with flags f and neighbour indices nb.
-template <class L, class T, class SN>
+template <class L, class T, class SN, bool PULL = false>
 __device__ __forceinline__ void colour_compact_core(const SN* __restrict__ N, const T* __restrict__ phi_prev,
                                                     const T* __restrict__ G, const uint8_t* __restrict__ flags,
                                                     T* __restrict__ phi, const KParams<T, L::Q>& P, uint32_t x,
@@ -576,7 +589,7 @@ __device__ __forceinline__ void colour_compact_core(const SN* __restrict__ N, co
     T acc = 0;
     static_for<0, L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        acc += compact_B<L, T, SN, i>(N, phi_prev, G, flags, P, x, nb, near);
+        acc += compact_B<L, T, SN, i, PULL>(N, phi_prev, G, flags, P, x, nb, near);
     });
     st(phi, x, acc);
 }
@@ -801,8 +814,12 @@ __global__ __launch_bounds__(256) void k_ghost(const int32_t* __restrict__ g_nod
 
 // Fused stencil + forces + collision + recolouring + push streaming with
 // halfway bounce-back, one node.  Writes the streamed N* and the node's
-// compact liquid record (G, p).
-template <class L, class T, class SN, bool NT = true>
+// compact liquid record (G, p).  PULL (fluid-only layout): the node gathers
+// its post-stream N from the post-collision slots of its sources (slot i of
+// x - c_i, or slot opp(i) of x at a bounce-back link) and stores its own
+// post-collision N* in its own slots, so the stores are contiguous and the
+// scattered accesses are reads.
+template <class L, class T, class SN, bool NT = true, bool PULL = false>
 __device__ __forceinline__ void collide_core(const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
                                              T* __restrict__ Gdst, const T* __restrict__ phi,
                                              const uint8_t* __restrict__ flags, const KParams<T, L::Q>& P,
@@ -811,8 +828,21 @@ __device__ __forceinline__ void collide_core(const SN* __restrict__ Nsrc, SN* __
     using NS = NStore<T, SN>;
     const int64_t S = P.S;
     T N[Q], ph[Q];
+    if constexpr (PULL) {
+        const bool near = (f & FLAG_NEAR_SOLID) != 0;
+        N[0] = NS::dec(ld(Nsrc, x), P.n_s);
+        static_for<1, Q>([&](auto ic) {
+            constexpr int i = decltype(ic)::value;
+            constexpr int j = L::opp[i];
+            const uint32_t src = nb[j];
+            const bool bounce = near && (ld(flags, src) & FLAG_SOLID);
+            N[i] = NS::dec(bounce ? ld(Nsrc + (int64_t)j * S, x) : ld(Nsrc + (int64_t)i * S, src), P.n_s);
+        });
+    } else {
 #pragma unroll
-    for (int i = 0; i < Q; i++) N[i] = NS::dec(NT ? ld_nt(Nsrc + (int64_t)i * S, x) : ld(Nsrc + (int64_t)i * S, x), P.n_s);
+        for (int i = 0; i < Q; i++)
+            N[i] = NS::dec(NT ? ld_nt(Nsrc + (int64_t)i * S, x) : ld(Nsrc + (int64_t)i * S, x), P.n_s);
+    }
 #pragma unroll
     for (int i = 0; i < Q; i++) ph[i] = ld(phi, nb[i]);
     Macro<T> m;
@@ -829,7 +859,10 @@ __device__ __forceinline__ void collide_core(const SN* __restrict__ Nsrc, SN* __
         closure -= NS::off(e[i]);
     }
     e[0] = NS::enc_off(closure);
-    if (f & FLAG_NEAR_SOLID) {
+    if constexpr (PULL) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) st(Ndst + (int64_t)i * S, x, e[i]);
+    } else if (f & FLAG_NEAR_SOLID) {
         static_for<0, Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             if (ld(flags, nb[i]) & FLAG_SOLID) st(Ndst + (int64_t)L::opp[i] * S, x, e[i]);
@@ -1379,7 +1412,7 @@ __global__ __launch_bounds__(256) void k_colour_sparse(const uint32_t* __restric
     if (k >= nf) return;
     uint32_t nb[L::Q];
     sparse_neighbours<L>(nbt, nf, (uint32_t)k, nb);
-    colour_compact_core<L, T, SN>(N, phi_prev, G, flags, phi, P, (uint32_t)k, ld(flags, (uint32_t)k), nb);
+    colour_compact_core<L, T, SN, true>(N, phi_prev, G, flags, phi, P, (uint32_t)k, ld(flags, (uint32_t)k), nb);
 }
 
 template <class L, class T, class SN>
@@ -1391,7 +1424,7 @@ __global__ __launch_bounds__(256) void k_collide_sparse(const uint32_t* __restri
     if (k >= nf) return;
     uint32_t nb[L::Q];
     sparse_neighbours<L>(nbt, nf, (uint32_t)k, nb);
-    collide_core<L, T, SN>(Nsrc, Ndst, Gdst, phi, flags, P, (uint32_t)k, ld(flags, (uint32_t)k), nb);
+    collide_core<L, T, SN, false, true>(Nsrc, Ndst, Gdst, phi, flags, P, (uint32_t)k, ld(flags, (uint32_t)k), nb);
 }
 
 // u and p of every slot (solid slots get 0), sparse layout.
@@ -1414,8 +1447,16 @@ __global__ __launch_bounds__(256) void k_macro_sparse(const uint32_t* __restrict
     uint32_t nb[Q];
     sparse_neighbours<L>(nbt, nf, (uint32_t)x, nb);
     T N[Q], ph[Q];
-#pragma unroll
-    for (int i = 0; i < Q; i++) N[i] = NStore<T, SN>::dec(Nsrc[(int64_t)i * S + x], P.n_s);
+    // post-stream N gathered from the post-collision slots (pull storage)
+    const bool near = (flags[x] & FLAG_NEAR_SOLID) != 0;
+    N[0] = NStore<T, SN>::dec(Nsrc[x], P.n_s);
+    static_for<1, Q>([&](auto ic) {
+        constexpr int i = decltype(ic)::value;
+        constexpr int j = L::opp[i];
+        const uint32_t src = nb[j];
+        const bool bounce = near && (flags[src] & FLAG_SOLID);
+        N[i] = NStore<T, SN>::dec(bounce ? Nsrc[(int64_t)j * S + x] : Nsrc[(int64_t)i * S + src], P.n_s);
+    });
 #pragma unroll
     for (int i = 0; i < Q; i++) ph[i] = phi[nb[i]];
     Macro<T> m;
@@ -1447,7 +1488,7 @@ __global__ __launch_bounds__(256) void k_compact_B_sparse(const uint32_t* __rest
     T v = 0;
     static_for<0, L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        if (i == dir) v = compact_B<L, T, SN, i>(N, phi_prev, G, flags, P, (uint32_t)x, nb, near);
+        if (i == dir) v = compact_B<L, T, SN, i, true>(N, phi_prev, G, flags, P, (uint32_t)x, nb, near);
     });
     out[x] = (double)v;
 }
@@ -1648,6 +1689,50 @@ __global__ __launch_bounds__(256) void k_nplane_in(const double* __restrict__ sr
     const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (x >= n) return;
     dst[x] = NStore<T, SN>::enc((T)(src[x] - (double)chi), inv_s);
+}
+
+// The same for the fluid-only layout, whose N holds post-collision
+// populations at their source slot: the post-stream N_i of fluid slot y is
+// slot i of y - c_i (nbo[y], the neighbour table's plane for opp(i)), or
+// slot opp(i) of y when y - c_i is solid.  Every stored slot of a fluid node
+// is the post-stream value of exactly one (i, y), so the read-out gathers
+// and the set scatters, both without arithmetic.  dir 0 has no source.
+template <class T, class SN>
+__global__ __launch_bounds__(256) void k_nplane_out_pull(const SN* __restrict__ N, const uint32_t* __restrict__ nbo,
+                                                         const uint8_t* __restrict__ flags, int dir, int odir,
+                                                         int64_t S, int64_t nf, T chi, T s,
+                                                         double* __restrict__ dst, int64_t n) {
+    const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= n) return;
+    if (y >= nf || (flags[y] & FLAG_SOLID)) {
+        dst[y] = 0.0;
+        return;
+    }
+    SN v;
+    if (dir == 0) {
+        v = N[y];
+    } else {
+        const uint32_t src = nbo[y];
+        v = (flags[src] & FLAG_SOLID) ? N[(int64_t)odir * S + y] : N[(int64_t)dir * S + src];
+    }
+    dst[y] = (double)chi + (double)NStore<T, SN>::dec(v, s);
+}
+
+template <class T, class SN>
+__global__ __launch_bounds__(256) void k_nplane_in_pull(const double* __restrict__ src, SN* __restrict__ N,
+                                                        const uint32_t* __restrict__ nbo,
+                                                        const uint8_t* __restrict__ flags, int dir, int odir,
+                                                        int64_t S, int64_t nf, T chi, T inv_s, int64_t n) {
+    const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= n || y >= nf || (flags[y] & FLAG_SOLID)) return;
+    const SN v = NStore<T, SN>::enc((T)(src[y] - (double)chi), inv_s);
+    if (dir == 0) {
+        N[y] = v;
+        return;
+    }
+    const uint32_t from = nbo[y];
+    if (flags[from] & FLAG_SOLID) N[(int64_t)odir * S + y] = v;
+    else N[(int64_t)dir * S + from] = v;
 }
 
 template <class T>
@@ -2006,6 +2091,14 @@ static hipError_t plane_out_t(const DevState& d, const StepParams& p, int which,
                            (const T*)d.phi[ps], (const T*)d.G[cur], d.flags, kp, dir, d.aux);
         return hipGetLastError();
     }
+    if ((which == 0 || which == 3) && d.sparse) {
+        const int odir = L::opp[dir];
+        hipLaunchKernelGGL((k_nplane_out_pull<T, SN>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st,
+                           (const SN*)d.N[cur], d.nbt + (int64_t)(odir > 0 ? odir - 1 : 0) * d.n_fluid, d.flags, dir,
+                           odir, p.S, d.n_fluid, which == 0 ? (T)p.chi[dir] : T(0),
+                           (T)(NStore<T, SN>::scaled ? N16_SCALE : 1.0), d.aux, p.n);
+        return hipGetLastError();
+    }
     if (which == 0 || which == 3) {
         hipLaunchKernelGGL((k_nplane_out<T, SN>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st,
                            (const SN*)d.N[cur] + (int64_t)dir * p.S, d.flags, which == 0 ? (T)p.chi[dir] : T(0),
@@ -2031,6 +2124,14 @@ static hipError_t plane_in_t(const DevState& d, const StepParams& p, int which, 
     if (which == 2) {
         hipLaunchKernelGGL((k_solid_in<T>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st, d.aux, d.flags,
                            (T*)d.phi[0], (T*)d.phi[1], p.n);
+        return hipGetLastError();
+    }
+    if ((which == 0 || which == 3) && d.sparse) {
+        const int odir = L::opp[dir];
+        hipLaunchKernelGGL((k_nplane_in_pull<T, SN>), dim3(blocks_for(p.n, 256)), dim3(256), 0, st, d.aux,
+                           (SN*)d.N[cur], d.nbt + (int64_t)(odir > 0 ? odir - 1 : 0) * d.n_fluid, d.flags, dir, odir,
+                           p.S, d.n_fluid, which == 0 ? (T)p.chi[dir] : T(0),
+                           (T)(NStore<T, SN>::scaled ? 1.0 / N16_SCALE : 1.0), p.n);
         return hipGetLastError();
     }
     if (which == 0 || which == 3) {
