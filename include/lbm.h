@@ -111,8 +111,8 @@ enum { LBM_FP64 = 0, LBM_FP32 = 1, LBM_FP16_OFS = 2, LBM_BF16_OFS = 3 };
  * every device plane holds one entry per slot instead of per box node.  The
  * slots are the fluid nodes in box order, then the ghost nodes in list
  * order, then one slot that stands for every other solid node.  A table of
- * Q - 1 slot indices per fluid node (4 (Q - 1) bytes) gives each fluid
- * node's neighbours.  Launches cover the fluid slots only, and a step
+ * Q - 1 slot indices per fluid node (4 (Q - 1) bytes, bit 31 marking a
+ * solid neighbour) gives each fluid node's neighbours.  Launches cover the fluid slots only, and a step
  * computes the same values as the box layout, bit for bit.  Streaming is
  * pull: the device keeps each node's post-collision populations in its own
  * slots and the next step gathers them (Eq. A16-A17 applied on read).

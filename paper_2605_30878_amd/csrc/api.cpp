@@ -506,7 +506,10 @@ int lbm_set_geometry(lbm_ctx* c, const lbm_solid* solids, int32_t count) {
             for (int i = 1; i < Q; i++) {
                 const int64_t nb = id_of(wrapi(x + cv[i][0], nx), wrapi(y + cv[i][1], ny),
                                          D == 3 ? wrapi(z + cv[i][2], nz) : 0);
-                c->nbt[(size_t)(i - 1) * nf + f] = (uint32_t)c->slot_of[nb];
+                // bit 31 marks a solid neighbour (a bounce-back link); the
+                // size check above keeps slots below 2^30
+                c->nbt[(size_t)(i - 1) * nf + f] =
+                    (uint32_t)c->slot_of[nb] | ((c->flags[nb] & FLAG_SOLID) ? 0x80000000u : 0u);
             }
         }
         c->M = M;

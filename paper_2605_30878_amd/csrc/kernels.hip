@@ -523,15 +523,16 @@ __device__ __forceinline__ T compact_term(T n, T phi_src, T gx, T gy, T gz, T p,
 
 // Post-stream liquid population B_i(y) from the compact record.  nb[i] is
 // y + c_i, so the source y - c_i is nb[opp(i)]; at a bounce-back link the
-// source is y with c_i reversed.  PULL: N holds post-collision populations
-// at their source node (fluid-only layout), so the post-stream N_i(y) is
-// read at the same source as the record: slot i of y - c_i, or slot opp(i)
-// of y at a bounce-back link.
+// source is y with c_i reversed.  PULL (fluid-only layout): N holds
+// post-collision populations at their source node, so the post-stream
+// N_i(y) is read at the same source as the record: slot i of y - c_i, or
+// slot opp(i) of y at a bounce-back link; and the solid links come from
+// the neighbour table (`links` bit i: y + c_i is solid), not from flags.
 template <class L, class T, class SN, int I, bool PULL = false>
 __device__ __forceinline__ T compact_B(const SN* __restrict__ N, const T* __restrict__ phi_prev,
                                        const T* __restrict__ G, const uint8_t* __restrict__ flags,
                                        const KParams<T, L::Q>& P, uint32_t y, const uint32_t (&nb)[L::Q],
-                                       bool near_solid) {
+                                       bool near_solid, uint32_t links = 0) {
     const int64_t S = P.S;
     if constexpr (I == 0) {
         const T n = NStore<T, SN>::dec(ld(N, y), P.n_s);
@@ -540,11 +541,12 @@ __device__ __forceinline__ T compact_B(const SN* __restrict__ N, const T* __rest
         constexpr int cx = L::c[I][0], cy = L::c[I][1], cz = L::c[I][2];
         uint32_t src = nb[L::opp[I]];
         T sgn = T(1);
-        bool bounce = false;
-        if (near_solid && (ld(flags, src) & FLAG_SOLID)) {
+        bool bounce;
+        if constexpr (PULL) bounce = (links >> L::opp[I]) & 1u;
+        else bounce = near_solid && (ld(flags, src) & FLAG_SOLID);
+        if (bounce) {
             src = y;
             sgn = T(-1);
-            bounce = true;
         }
         T n;
         if constexpr (PULL)
@@ -584,12 +586,12 @@ template <class L, class T, class SN, bool PULL = false>
 __device__ __forceinline__ void colour_compact_core(const SN* __restrict__ N, const T* __restrict__ phi_prev,
                                                     const T* __restrict__ G, const uint8_t* __restrict__ flags,
                                                     T* __restrict__ phi, const KParams<T, L::Q>& P, uint32_t x,
-                                                    uint8_t f, const uint32_t (&nb)[L::Q]) {
+                                                    uint8_t f, const uint32_t (&nb)[L::Q], uint32_t links = 0) {
     const bool near = (f & FLAG_NEAR_SOLID) != 0;
     T acc = 0;
     static_for<0, L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        acc += compact_B<L, T, SN, i, PULL>(N, phi_prev, G, flags, P, x, nb, near);
+        acc += compact_B<L, T, SN, i, PULL>(N, phi_prev, G, flags, P, x, nb, near, links);
     });
     st(phi, x, acc);
 }
@@ -818,25 +820,25 @@ __global__ __launch_bounds__(256) void k_ghost(const int32_t* __restrict__ g_nod
 // its post-stream N from the post-collision slots of its sources (slot i of
 // x - c_i, or slot opp(i) of x at a bounce-back link) and stores its own
 // post-collision N* in its own slots, so the stores are contiguous and the
-// scattered accesses are reads.
+// scattered accesses are reads.  Its solid links come from the neighbour
+// table (`links` bit i: x + c_i is solid).
 template <class L, class T, class SN, bool NT = true, bool PULL = false>
 __device__ __forceinline__ void collide_core(const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
                                              T* __restrict__ Gdst, const T* __restrict__ phi,
                                              const uint8_t* __restrict__ flags, const KParams<T, L::Q>& P,
-                                             uint32_t x, uint8_t f, const uint32_t (&nb)[L::Q]) {
+                                             uint32_t x, uint8_t f, const uint32_t (&nb)[L::Q],
+                                             uint32_t links = 0) {
     constexpr int Q = L::Q;
     using NS = NStore<T, SN>;
     const int64_t S = P.S;
     T N[Q], ph[Q];
     if constexpr (PULL) {
-        const bool near = (f & FLAG_NEAR_SOLID) != 0;
         N[0] = NS::dec(ld(Nsrc, x), P.n_s);
         static_for<1, Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
             constexpr int j = L::opp[i];
-            const uint32_t src = nb[j];
-            const bool bounce = near && (ld(flags, src) & FLAG_SOLID);
-            N[i] = NS::dec(bounce ? ld(Nsrc + (int64_t)j * S, x) : ld(Nsrc + (int64_t)i * S, src), P.n_s);
+            const bool bounce = (links >> j) & 1u;
+            N[i] = NS::dec(bounce ? ld(Nsrc + (int64_t)j * S, x) : ld(Nsrc + (int64_t)i * S, nb[j]), P.n_s);
         });
     } else {
 #pragma unroll
@@ -1392,15 +1394,23 @@ __global__ __launch_bounds__(256) void k_colour_fixup(T* __restrict__ phi_out, c
 // (ascending box index), then the ghost nodes, then one slot that stands
 // for every other solid node; every plane has one entry per slot.
 // nbt[(i - 1) n_fluid + k] is the slot of fluid node k + c_i (a ghost slot
-// where the neighbour is solid).  The per-node functions are the box
-// layout's, so a step computes the same values bit for bit; only the
-// launches cover the fluid slots instead of the box.
+// where the neighbour is solid), with NBT_SOLID set where it is solid, so
+// that the bounce-back links need no load of the neighbour's flags.  The
+// per-node functions are the box layout's, so a step computes the same
+// values bit for bit; only the launches cover the fluid slots instead of
+// the box.
+constexpr uint32_t NBT_SOLID = 0x80000000u, NBT_SLOT = 0x7FFFFFFFu;
 template <class L>
 __device__ __forceinline__ void sparse_neighbours(const uint32_t* __restrict__ nbt, int64_t nf, uint32_t k,
-                                                  uint32_t (&nb)[L::Q]) {
+                                                  uint32_t (&nb)[L::Q], uint32_t& links) {
     nb[0] = k;
+    links = 0;
 #pragma unroll
-    for (int i = 1; i < L::Q; i++) nb[i] = nbt[(int64_t)(i - 1) * nf + k];
+    for (int i = 1; i < L::Q; i++) {
+        const uint32_t e = nbt[(int64_t)(i - 1) * nf + k];
+        nb[i] = e & NBT_SLOT;
+        links |= (e >> 31) << i;
+    }
 }
 
 template <class L, class T, class SN>
@@ -1410,9 +1420,9 @@ __global__ __launch_bounds__(256) void k_colour_sparse(const uint32_t* __restric
                                                        T* __restrict__ phi, KParams<T, L::Q> P) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nf) return;
-    uint32_t nb[L::Q];
-    sparse_neighbours<L>(nbt, nf, (uint32_t)k, nb);
-    colour_compact_core<L, T, SN, true>(N, phi_prev, G, flags, phi, P, (uint32_t)k, ld(flags, (uint32_t)k), nb);
+    uint32_t nb[L::Q], links;
+    sparse_neighbours<L>(nbt, nf, (uint32_t)k, nb, links);
+    colour_compact_core<L, T, SN, true>(N, phi_prev, G, flags, phi, P, (uint32_t)k, 0, nb, links);
 }
 
 template <class L, class T, class SN>
@@ -1422,9 +1432,9 @@ __global__ __launch_bounds__(256) void k_collide_sparse(const uint32_t* __restri
                                                         const uint8_t* __restrict__ flags, KParams<T, L::Q> P) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nf) return;
-    uint32_t nb[L::Q];
-    sparse_neighbours<L>(nbt, nf, (uint32_t)k, nb);
-    collide_core<L, T, SN, false, true>(Nsrc, Ndst, Gdst, phi, flags, P, (uint32_t)k, ld(flags, (uint32_t)k), nb);
+    uint32_t nb[L::Q], links;
+    sparse_neighbours<L>(nbt, nf, (uint32_t)k, nb, links);
+    collide_core<L, T, SN, false, true>(Nsrc, Ndst, Gdst, phi, flags, P, (uint32_t)k, 0, nb, links);
 }
 
 // u and p of every slot (solid slots get 0), sparse layout.
@@ -1444,18 +1454,16 @@ __global__ __launch_bounds__(256) void k_macro_sparse(const uint32_t* __restrict
         aux[3 * S + x] = 0.0;
         return;
     }
-    uint32_t nb[Q];
-    sparse_neighbours<L>(nbt, nf, (uint32_t)x, nb);
+    uint32_t nb[Q], links;
+    sparse_neighbours<L>(nbt, nf, (uint32_t)x, nb, links);
     T N[Q], ph[Q];
     // post-stream N gathered from the post-collision slots (pull storage)
-    const bool near = (flags[x] & FLAG_NEAR_SOLID) != 0;
     N[0] = NStore<T, SN>::dec(Nsrc[x], P.n_s);
     static_for<1, Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
         constexpr int j = L::opp[i];
-        const uint32_t src = nb[j];
-        const bool bounce = near && (flags[src] & FLAG_SOLID);
-        N[i] = NStore<T, SN>::dec(bounce ? Nsrc[(int64_t)j * S + x] : Nsrc[(int64_t)i * S + src], P.n_s);
+        const bool bounce = (links >> j) & 1u;
+        N[i] = NStore<T, SN>::dec(bounce ? Nsrc[(int64_t)j * S + x] : Nsrc[(int64_t)i * S + nb[j]], P.n_s);
     });
 #pragma unroll
     for (int i = 0; i < Q; i++) ph[i] = phi[nb[i]];
@@ -1482,13 +1490,12 @@ __global__ __launch_bounds__(256) void k_compact_B_sparse(const uint32_t* __rest
         out[x] = 0.0;
         return;
     }
-    uint32_t nb[L::Q];
-    sparse_neighbours<L>(nbt, nf, (uint32_t)x, nb);
-    const bool near = (f & FLAG_NEAR_SOLID) != 0;
+    uint32_t nb[L::Q], links;
+    sparse_neighbours<L>(nbt, nf, (uint32_t)x, nb, links);
     T v = 0;
     static_for<0, L::Q>([&](auto ic) {
         constexpr int i = decltype(ic)::value;
-        if (i == dir) v = compact_B<L, T, SN, i, true>(N, phi_prev, G, flags, P, (uint32_t)x, nb, near);
+        if (i == dir) v = compact_B<L, T, SN, i, true>(N, phi_prev, G, flags, P, (uint32_t)x, nb, false, links);
     });
     out[x] = (double)v;
 }
@@ -1712,8 +1719,8 @@ __global__ __launch_bounds__(256) void k_nplane_out_pull(const SN* __restrict__ 
     if (dir == 0) {
         v = N[y];
     } else {
-        const uint32_t src = nbo[y];
-        v = (flags[src] & FLAG_SOLID) ? N[(int64_t)odir * S + y] : N[(int64_t)dir * S + src];
+        const uint32_t e = nbo[y];
+        v = (e & NBT_SOLID) ? N[(int64_t)odir * S + y] : N[(int64_t)dir * S + (e & NBT_SLOT)];
     }
     dst[y] = (double)chi + (double)NStore<T, SN>::dec(v, s);
 }
@@ -1730,9 +1737,9 @@ __global__ __launch_bounds__(256) void k_nplane_in_pull(const double* __restrict
         N[y] = v;
         return;
     }
-    const uint32_t from = nbo[y];
-    if (flags[from] & FLAG_SOLID) N[(int64_t)odir * S + y] = v;
-    else N[(int64_t)dir * S + from] = v;
+    const uint32_t e = nbo[y];
+    if (e & NBT_SOLID) N[(int64_t)odir * S + y] = v;
+    else N[(int64_t)dir * S + (e & NBT_SLOT)] = v;
 }
 
 template <class T>
