@@ -116,7 +116,7 @@ def test_small_served_mix_matches_single_runs():
         s.close()
 
 
-@pytest.mark.parametrize("prec", [W.FP32, W.FP16_OFS], ids=["f32", "fp16ofs"])
+@pytest.mark.parametrize("prec", [W.FP32, W.FP16_OFS, W.BF16_OFS], ids=["f32", "fp16ofs", "bf16ofs"])
 def test_batch_after_tiled_single_steps(prec):
     """A 64^3 run stepped alone (tiled colour kernel), then in a batch (row
     kernels over the job table), then alone again equals the same run
