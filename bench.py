@@ -236,10 +236,11 @@ def hot_path(args, precision: str, form: str, layout: str) -> dict:
         impl_bytes = 2 * Q * s_n + 2 * s_t + (2 * inbox * s_t) / wl.nodes + 1
         kernel = "k_collide_colour"
     elif layout == "sparse":
-        # the same per fluid node; flags are read per fluid slot, and the
-        # neighbour-slot table ((Q - 1) x 4 bytes per fluid node, read by both
-        # launches) is layout overhead, counted in impl_bytes only
-        alg_bytes = n_fluid * (2 * Q * s_n + s_t + (D + 1) * s_t + 1)
+        # the same per fluid node, with no flag bytes (the bounce-back links
+        # come with the neighbour slots); the neighbour-slot table ((Q - 1) x
+        # 4 bytes per fluid node, read by both launches) is layout overhead,
+        # counted in impl_bytes only
+        alg_bytes = n_fluid * (2 * Q * s_n + s_t + (D + 1) * s_t)
         impl_bytes = ((Q * s_n + 2 * s_t + (D + 1) * s_t) + (2 * Q * s_n + s_t + (D + 1) * s_t)
                       + 2 * (Q - 1) * 4)
         kernel = "k_collide_sparse"
