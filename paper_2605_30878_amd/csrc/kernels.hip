@@ -862,8 +862,10 @@ __device__ __forceinline__ void collide_core(const SN* __restrict__ Nsrc, SN* __
     }
     e[0] = NS::enc_off(closure);
     if constexpr (PULL) {
+        // whole lines that this launch does not read again: non-temporal,
+        // so that they do not push the gathered source lines out of L2
 #pragma unroll
-        for (int i = 0; i < Q; i++) st(Ndst + (int64_t)i * S, x, e[i]);
+        for (int i = 0; i < Q; i++) __builtin_nontemporal_store(e[i], Ndst + (int64_t)i * S + x);
     } else if (f & FLAG_NEAR_SOLID) {
         static_for<0, Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
