@@ -101,6 +101,11 @@ template <class V>
 __device__ __forceinline__ void st(V* __restrict__ base, uint32_t idx, V v) {
     *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(V)) = v;
 }
+// The same as a non-temporal store, for values the launch does not read again.
+template <class V>
+__device__ __forceinline__ void st_nt(V* __restrict__ base, uint32_t idx, V v) {
+    __builtin_nontemporal_store(v, reinterpret_cast<V*>(reinterpret_cast<char*>(base) + idx * (uint32_t)sizeof(V)));
+}
 
 // c * v for a lattice component c in {-1, 0, 1}, resolved at compile time.
 template <int C, class T>
@@ -865,7 +870,7 @@ __device__ __forceinline__ void collide_core(const SN* __restrict__ Nsrc, SN* __
         // whole lines that this launch does not read again: non-temporal,
         // so that they do not push the gathered source lines out of L2
 #pragma unroll
-        for (int i = 0; i < Q; i++) __builtin_nontemporal_store(e[i], Ndst + (int64_t)i * S + x);
+        for (int i = 0; i < Q; i++) st_nt(Ndst + (int64_t)i * S, x, e[i]);
     } else if (f & FLAG_NEAR_SOLID) {
         static_for<0, Q>([&](auto ic) {
             constexpr int i = decltype(ic)::value;
@@ -1130,7 +1135,10 @@ __global__ __launch_bounds__(KNT, sizeof(T) == 8 ? 2 : 4) void k_collide_colour(
                 closure -= NS::off(e[i]);
             }
             e[0] = NS::enc_off(closure);
-            st(Ndst, x, e[0]);   // the rest population stays at x
+            // N* goes out with non-temporal stores: the launch does not read
+            // it again, and the L2 then keeps the inbox values and the colour
+            // field that the fix-up reads next
+            st_nt(Ndst, x, e[0]);   // the rest population stays at x
             b0 = mc.phi * (P.chi[0] + NS::dec(e[0], P.n_s));
             // every direction streams to x + c_i; where that node is solid
             // the value lands in an entry that nothing reads (a solid node's
@@ -1140,7 +1148,7 @@ __global__ __launch_bounds__(KNT, sizeof(T) == 8 ? 2 : 4) void k_collide_colour(
                 constexpr int i = decltype(ic)::value;
                 constexpr int cx = L::c[i][0], cy = L::c[i][1], cz = L::c[i][2];
                 const T b = compact_term<L, T, i>(NS::dec(e[i], P.n_s), mc.phi, G[0], G[1], G[2], mc.p, T(1), P);
-                st(Ndst, (uint32_t)i * S32 + nbr(ic), e[i]);
+                st_nt(Ndst, (uint32_t)i * S32 + nbr(ic), e[i]);
                 // the branches on ty and lz are wave-uniform
                 const bool y_out = cy != 0 && (ty + cy < 0 || ty + cy >= KTY);
                 const bool z_out = cz != 0 && (lz + cz < 0 || lz + cz >= zlen);
