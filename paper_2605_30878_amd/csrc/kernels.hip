@@ -826,7 +826,8 @@ __global__ __launch_bounds__(256) void k_ghost(const int32_t* __restrict__ g_nod
 // x - c_i, or slot opp(i) of x at a bounce-back link) and stores its own
 // post-collision N* in its own slots, so the stores are contiguous and the
 // scattered accesses are reads.  Its solid links come from the neighbour
-// table (`links` bit i: x + c_i is solid).
+// table (`links` bit i: x + c_i is solid).  NT (single runs): N is loaded
+// and the record stored non-temporally.
 template <class L, class T, class SN, bool NT = true, bool PULL = false>
 __device__ __forceinline__ void collide_core(const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
                                              T* __restrict__ Gdst, const T* __restrict__ phi,
@@ -881,9 +882,17 @@ __device__ __forceinline__ void collide_core(const SN* __restrict__ Nsrc, SN* __
 #pragma unroll
         for (int i = 0; i < Q; i++) st(Ndst + (int64_t)i * S, nb[i], e[i]);
     }
+    if constexpr (NT) {
+        // single runs: the record is read only by the next step's colour
+        // pass, after this launch has streamed the whole box
 #pragma unroll
-    for (int a = 0; a < L::D; a++) st(Gdst + (int64_t)a * S, x, G[a]);
-    st(Gdst + (int64_t)GRec<L>::P * S, x, m.p);
+        for (int a = 0; a < L::D; a++) st_nt(Gdst + (int64_t)a * S, x, G[a]);
+        st_nt(Gdst + (int64_t)GRec<L>::P * S, x, m.p);
+    } else {
+#pragma unroll
+        for (int a = 0; a < L::D; a++) st(Gdst + (int64_t)a * S, x, G[a]);
+        st(Gdst + (int64_t)GRec<L>::P * S, x, m.p);
+    }
 }
 template <class L, class T, class SN, bool NT = true>
 __device__ __forceinline__ void collide_node(const SN* __restrict__ Nsrc, SN* __restrict__ Ndst,
