@@ -1394,7 +1394,8 @@ __global__ __launch_bounds__(256) void k_colour_fixup(T* __restrict__ phi_out, c
         if constexpr (cz != 0) zs = 10 * cg.zc * (KTX + KTY) + ((cz > 0 ? 0 : 5) + cross_k<i, 2, cz>()) * KNT + zrow;
         const int slot = xc ? xs : (yc ? ys : zs);
         v[i - 1] = T(0);
-        if (xc || yc || zc) v[i - 1] = box[slot];
+        // the inbox's last read this step: non-temporal
+        if (xc || yc || zc) v[i - 1] = __builtin_nontemporal_load(box + slot);
     });
     if (fx & FLAG_SOLID) return;
     T add = T(0);
