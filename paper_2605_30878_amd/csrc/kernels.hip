@@ -478,12 +478,13 @@ __device__ __forceinline__ bool row_index(int nx, int ny, RowIdx& r) {
 // the y +- 1 and z +- 1 neighbour rows a stencil reads are mostly in its own
 // L2 (the row-major order spreads y-neighbours over three XCDs, each fetching
 // the row again).  Any order computes the same result.
+// rev: blocks take the rows in reverse order (last plane first).
 struct RowSched {
-    int xb, ny, band;
+    int xb, ny, band, rev;
 };
 
 __device__ __forceinline__ bool row_index_sched(const RowSched& s, int nx, RowIdx& r) {
-    const int64_t L = blockIdx.x;
+    const int64_t L = s.rev ? (int64_t)gridDim.x - 1 - blockIdx.x : (int64_t)blockIdx.x;
     int64_t bxi, y, z;
     if (s.band > 0) {
         const int64_t j = L >> 3;
@@ -1903,6 +1904,7 @@ static inline RowSched row_sched(const StepParams& p, int bx) {
     s.xb = (p.nx + bx - 1) / bx;
     s.ny = p.ny;
     s.band = 0;
+    s.rev = 0;
     return s;
 }
 
@@ -2017,7 +2019,7 @@ static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int
                 ts.xt = g.xt;
                 ts.yt = g.yt;
                 ts.band = g.yt % 8 == 0 ? g.yt / 8 : 0;
-                const unsigned nb = (unsigned)(g.xt * g.yt * ((p.nz + g.zc - 1) / g.zc));
+                const unsigned nb = (unsigned)(g.xt * g.yt * g.nzc);
                 hipLaunchKernelGGL((k_collide_colour<T, SN>), dim3(nb), dim3(KNT), 0, st, (const SN*)d.N[cur],
                                    (SN*)d.N[1 - cur], (const T*)work, (T*)d.phi[ps], (T*)d.cross, d.flags, kp, ts, g);
                 return hipGetLastError();
@@ -2030,7 +2032,11 @@ static hipError_t phase_t(int phase, const DevState& d, const StepParams& p, int
                                    (const T*)work, d.flags, kp);
             return hipGetLastError();
         }
-        const RowSched rs = row_sched(p, bx);
+        // rows from the last plane down: the launch ends on the first planes,
+        // where the next step's colour pass starts while the last-level
+        // cache still holds what was stored there last (N*, the record)
+        RowSched rs = row_sched(p, bx);
+        rs.rev = 1;
         hipLaunchKernelGGL((k_collide_stream<L, T, SN>), row_grid1(rs, p), dim3(bx), 0, st, (const SN*)d.N[cur],
                            (SN*)d.N[1 - cur], (T*)d.G[1 - cur], (const T*)work, d.flags, kp, rs);
     } else {
